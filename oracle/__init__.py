@@ -1,0 +1,16 @@
+"""FP64 CPU oracle of the impact-based fair ranking solver.
+
+TEST INFRASTRUCTURE ONLY: this package is the slow, plain reference against
+which the GPU library is checked.  Only the test suite, the package's smoke
+check and the benchmark's CPU-baseline leg may import it.  It shares no code
+with the GPU path (``paper_2406_10262_amd``) and never imports it.
+
+* ``oracle.core``  -- ctypes wrapper of ``fr_oracle.c`` (Sinkhorn forward,
+  impacts, NSW, reverse-mode gradient, Adam / gradient ascent, Algorithm 1).
+* ``oracle.brute`` -- NumPy brute-force optima and closed forms for tiny
+  instances, used to pin the oracle itself.
+"""
+from .core import (  # noqa: F401
+    build_oracle, forward, forward_converge, impact, nsw, grad, adam, gd, solve,
+    num_threads, library_path,
+)
