@@ -1,0 +1,177 @@
+/*
+ * fairrank.h -- C ABI of the MI355X (gfx950) impact-based fair ranking solver.
+ *
+ * The solver implements the gradient-ascent method of Uehara et al., "Fast
+ * solution to the fair ranking problem using the Sinkhorn algorithm":
+ *
+ *   * Section 2 (problem nsw): one plan X_u in R^{I x m} per consumer u, rows
+ *     summing to 1 (Eq. dsm1), the m-1 real position columns summing to 1
+ *     (Eq. dsm2), x >= 0 (Eq. dsm4), and the last column a dummy position
+ *     whose column sums to I - m + 1.  Item impact (Eq. Imp)
+ *         Imp_i = sum_u sum_{k<m} r(u,i) e(k) x_uik
+ *     and objective (Eq. objF) F = sum_i log Imp_i  (log of the Nash social
+ *     welfare).
+ *   * Section 3 (problem otp): X_u is the entropic optimal transport plan of a
+ *     cost matrix C_u, computed by T log-domain Sinkhorn iterations from a cold
+ *     start; F is maximised over C (problem nsw2) by gradient ascent
+ *     (Algorithm 1), the gradient taken by the chain rule through the T
+ *     iterations, the step by Adam (Section 4.1) or plain ascent.
+ *
+ * Conventions shared by every entry point
+ *   * Pointers are DEVICE pointers unless marked (host).  Layouts are dense
+ *     row-major: C, X, dC, Adam moments [U][I][m] with m fastest; r, dr
+ *     [U][I]; potentials [U][I+m] (f then g); e [m-1]; impacts [I] (double).
+ *   * The caller owns and allocates every buffer, including the workspace
+ *     sized by fr_workspace_bytes; the library never frees caller memory.
+ *     A context owns only its launch-configuration (autotune) cache and its
+ *     captured graphs.
+ *   * All calls are asynchronous on the given stream (a hipStream_t passed
+ *     as void*; NULL = the default stream) unless documented otherwise.  A
+ *     context must not be used from two host threads at once.
+ *   * Every call returns an fr_status and never aborts.  Argument errors are
+ *     detected on the host and returned before anything is enqueued.
+ *     Conditions found on the device (a non-finite value, an impact <= 0) set
+ *     a flag word in the workspace; fr_solve reports them (it synchronises),
+ *     after the asynchronous calls fr_sync_status does.
+ *   * Sizes: 1 <= U, 2 <= m <= I (the dummy mass I-m+1 must be >= 1),
+ *     m <= 64, I <= 4096, eps > 0 finite, T >= 1.
+ */
+#ifndef FAIRRANK_H
+#define FAIRRANK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FR_OK = 0,
+    FR_E_NULL = 1,        /* a required pointer is NULL                          */
+    FR_E_SHAPE = 2,       /* sizes out of range (see above)                      */
+    FR_E_PARAM = 3,       /* eps, T, step counts or optimiser settings invalid   */
+    FR_E_WORKSPACE = 4,   /* workspace smaller than fr_workspace_bytes           */
+    FR_E_DEVICE = 5,      /* a HIP runtime call failed                           */
+    FR_E_NONFINITE = 6,   /* device found a NaN/Inf in an impact or objective    */
+    FR_E_ZERO_IMPACT = 7, /* device found Imp_i <= 0, so log Imp_i is undefined  */
+    FR_E_UNSUPPORTED = 8  /* valid request this build does not handle            */
+} fr_status;
+
+typedef enum { FR_F32 = 0, FR_BF16 = 1 } fr_dtype;   /* storage type of X     */
+typedef enum { FR_ADAM = 0, FR_GD = 1 } fr_rule;     /* ascent rule           */
+
+typedef struct fr_ctx fr_ctx;
+
+/* One fair-ranking instance (Section 2 notation). */
+typedef struct {
+    int64_t n_users;        /* |U| >= 1                                          */
+    int32_t n_items;        /* |I|, 2 <= |I| <= 4096                             */
+    int32_t m;              /* columns of X_u incl. the dummy, 2 <= m <= min(I,64)*/
+    const float* r;         /* [U][I] relevance r(u,i) (device)                   */
+    const float* e;         /* [m-1] exposure of the real positions (device)      */
+    float eps;              /* entropic weight of problem otp, > 0                */
+    int32_t sinkhorn_iters; /* T >= 1 full (row + column) iterations, cold start  */
+} fr_problem;
+
+/* Outer loop of Algorithm 1. */
+typedef struct {
+    int32_t rule;             /* fr_rule                                            */
+    float lr;                 /* step size (Adam lr, or ascent step for FR_GD)     */
+    float beta1, beta2;       /* Adam moment decays, e.g. 0.9 and 0.999            */
+    float adam_eps;           /* Adam denominator guard, e.g. 1e-8                 */
+    int32_t outer_steps;      /* N >= 0 ascent steps                               */
+    int32_t checkpoint_every; /* K: Sinkhorn potentials kept every K iterations for
+                                 the reverse sweep (1 = keep all, no recomputation;
+                                 0 = let the library choose)                       */
+} fr_optim;
+
+/* ---------------------------------------------------------------- context */
+/* Creates a context bound to HIP device `device` (made current by every call). */
+fr_status fr_ctx_create(int device, fr_ctx** out);
+void fr_ctx_destroy(fr_ctx* ctx);
+
+/* Bytes of workspace every call below needs for this problem (optim may be
+ * NULL: then K = 1 and no Adam state).  Written to *out (host). */
+fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size_t* out);
+
+/* Prepares a newly allocated workspace (clears its device flags and step
+ * counter; enqueued on the stream).  Call once per allocation, before the
+ * workspace's first use; the flags then persist across calls until
+ * fr_sync_status reads and clears them.  ws_bytes >= 256. */
+fr_status fr_workspace_init(fr_ctx* ctx, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- forward */
+/* Section 3 + Eqs. Imp, objF: X_u = Sinkhorn_T(C_u) for every consumer (T
+ * log-domain iterations from g = 0, each a row then a column half-step), then
+ * Imp and F.  C [U][I][m] float.  Outputs, each optional (NULL = not written):
+ * X [U][I][m] in x_dtype (BF16 rounds to nearest even; the impacts are always
+ * taken from the FP32 plan), pot [U][I+m] float potentials f then g in cost
+ * units, imp [I] double, F [1] double.  Impacts are summed over consumers in
+ * FP64 in a fixed order (bitwise reproducible). */
+fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
+                  fr_dtype x_dtype, float* pot, double* imp, double* F,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Eqs. Imp and objF for a given plan X [U][I][m] (x_dtype): imp [I] and F [1]
+ * (double, either optional).  X need not be a Sinkhorn output. */
+fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,
+                 double* imp, double* F, void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------- backward */
+/* Section 3 ("chain rule"): reverse mode through the T unrolled Sinkhorn
+ * iterations.  Given C and the impacts imp [I] of X(C) (from fr_step), writes
+ * dC = gF * dF/dC [U][I][m] and, if dr is not NULL, dr = gF * dF/dr [U][I].
+ * The forward is recomputed from C; potentials are kept every
+ * checkpoint_every iterations (>= 1) and the segments between them are
+ * recomputed during the reverse sweep. */
+fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const double* imp,
+                      double gF, float* dC, float* dr, int32_t checkpoint_every,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------- Algorithm 1 */
+/* N = optim->outer_steps ascent steps on C (in: C_0, out: C_N).  Step n runs
+ * the forward at C_n, records F_n, takes dF/dC and updates C.  A final forward
+ * gives X(C_N) and F_N, so F_hist [N+1] (double) holds F_0..F_N.  Adam state
+ * adam_m, adam_v [U][I][m] (in/out; zero them for a fresh start; ignored for
+ * FR_GD) and start_step (Adam's step count before this call) make a run of
+ * N1 steps followed by one of N2 steps identical to one run of N1+N2 steps.
+ * X_out (x_dtype, optional) receives X(C_N).  The step is captured once as a
+ * HIP graph and replayed N times.  Synchronises the stream before returning
+ * and reports device flags. */
+fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, float* C,
+                   float* adam_m, float* adam_v, int64_t start_step, void* X_out,
+                   fr_dtype x_dtype, double* F_hist, void* ws, size_t ws_bytes, void* stream);
+
+/* Same method, but one kernel launch per Sinkhorn half-iteration with the
+ * potentials in HBM and the reverse sweep reading every stored iterate: the
+ * unfused GPU form used as the performance baseline.  Same arguments and
+ * results as fr_solve (up to rounding); workspace from
+ * fr_workspace_bytes_plain. */
+fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, float* C,
+                         float* adam_m, float* adam_v, int64_t start_step, void* X_out,
+                         fr_dtype x_dtype, double* F_hist, void* ws, size_t ws_bytes,
+                         void* stream);
+fr_status fr_workspace_bytes_plain(const fr_problem* prob, size_t* out);
+
+/* ------------------------------------------------------------ utilities */
+/* Synchronises the stream and returns the device flags recorded in ws
+ * (FR_E_NONFINITE / FR_E_ZERO_IMPACT), then clears them. */
+fr_status fr_sync_status(fr_ctx* ctx, void* ws, void* stream);
+
+/* Static description of a status code. */
+const char* fr_status_string(fr_status s);
+
+/* Launch configuration of the fused kernels for plans of a given shape:
+ * lanes per consumer (1..64 as a power of two, or a multiple of 64 up to
+ * 1024) and plan rows held by each lane.  fr_set_launch overrides the
+ * library's choice for (I, m); fr_get_launch reports the current choice. */
+fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes,
+                        int32_t rows_per_lane);
+fr_status fr_get_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t* lanes,
+                        int32_t* rows_per_lane);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAIRRANK_H */

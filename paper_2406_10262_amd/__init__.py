@@ -1,0 +1,349 @@
+"""MI355X-native impact-based fair ranking solver.
+
+Python binding of ``libfairrank.so`` (C ABI in ``include/fairrank.h``).  This
+module only marshals arguments: every step of the method -- Sinkhorn on each
+consumer's plan (Section 3, problem otp), the impact and log-NSW sums
+(Eqs. Imp and objF), the reverse sweep through the Sinkhorn iterations and
+the ascent step of Algorithm 1 -- runs in the HIP library.  PyTorch supplies
+device memory and streams.
+
+The library must have been built (``python -m paper_2406_10262_amd.build``);
+every entry point raises if it cannot be loaded.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+__all__ = [
+    "load", "library_path", "FairRankError", "Context", "Problem", "step", "nsw",
+    "backward", "solve", "solve_plain", "SinkhornNSW", "sinkhorn_nsw",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfairrank.so")
+_lib = None
+
+FR_OK = 0
+FR_F32, FR_BF16 = 0, 1
+FR_ADAM, FR_GD = 0, 1
+STATUS = {
+    0: "FR_OK", 1: "FR_E_NULL", 2: "FR_E_SHAPE", 3: "FR_E_PARAM", 4: "FR_E_WORKSPACE",
+    5: "FR_E_DEVICE", 6: "FR_E_NONFINITE", 7: "FR_E_ZERO_IMPACT", 8: "FR_E_UNSUPPORTED",
+}
+
+
+class FairRankError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = _lib.fr_status_string(code).decode() if _lib is not None else ""
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({msg})")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_users", ctypes.c_int64), ("n_items", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("r", ctypes.c_void_p), ("e", ctypes.c_void_p), ("eps", ctypes.c_float),
+                ("sinkhorn_iters", ctypes.c_int32)]
+
+
+class _Optim(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("outer_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Loads libfairrank.so; raises FileNotFoundError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise FileNotFoundError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_2406_10262_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    PP = ctypes.POINTER(_Problem)
+    PO = ctypes.POINTER(_Optim)
+    lib.fr_status_string.restype = ctypes.c_char_p
+    lib.fr_status_string.argtypes = [ctypes.c_int]
+    lib.fr_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.fr_ctx_destroy.argtypes = [P]
+    lib.fr_ctx_destroy.restype = None
+    lib.fr_workspace_bytes.argtypes = [PP, PO, ctypes.POINTER(SZ)]
+    lib.fr_workspace_bytes_plain.argtypes = [PP, ctypes.POINTER(SZ)]
+    lib.fr_step.argtypes = [P, PP, P, P, ctypes.c_int, P, P, P, P, SZ, P]
+    lib.fr_nsw.argtypes = [P, PP, P, ctypes.c_int, P, P, P, SZ, P]
+    lib.fr_backward.argtypes = [P, PP, P, P, ctypes.c_double, P, P, I32, P, SZ, P]
+    lib.fr_solve.argtypes = [P, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
+    lib.fr_solve_plain.argtypes = [P, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
+    lib.fr_sync_status.argtypes = [P, P, P]
+    lib.fr_workspace_init.argtypes = [P, P, SZ, P]
+    lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
+    lib.fr_get_launch.argtypes = [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
+                 "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
+                 "fr_set_launch", "fr_get_launch"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int, what: str):
+    if code != FR_OK:
+        raise FairRankError(code, what)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+# --------------------------------------------------------------------------
+class Context:
+    """Owns an fr_ctx (launch-configuration cache) and a reusable workspace."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(lib.fr_ctx_create(device, ctypes.byref(h)), "fr_ctx_create")
+        self.handle = h
+        self._ws = None
+
+    def close(self):
+        if self.handle is not None and _lib is not None:
+            _lib.fr_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            _check(load().fr_workspace_init(self.handle, _ptr(ws), ws.numel(),
+                                            _stream(self.device)), "fr_workspace_init")
+            self._ws = ws
+        return self._ws
+
+    def set_launch(self, n_items: int, m: int, lanes: int, rows: int):
+        _check(load().fr_set_launch(self.handle, n_items, m, lanes, rows), "fr_set_launch")
+
+    def get_launch(self, n_items: int, m: int):
+        L, R = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().fr_get_launch(self.handle, n_items, m, ctypes.byref(L), ctypes.byref(R)),
+               "fr_get_launch")
+        return L.value, R.value
+
+
+@dataclass
+class Problem:
+    """One instance: r [U, I] and e [m-1] float32 tensors on the device."""
+    r: torch.Tensor
+    e: torch.Tensor
+    eps: float
+    T: int
+
+    @property
+    def U(self):
+        return self.r.shape[0]
+
+    @property
+    def I(self):
+        return self.r.shape[1]
+
+    @property
+    def m(self):
+        return self.e.shape[0] + 1
+
+    def c(self) -> _Problem:
+        for t, nm in ((self.r, "r"), (self.e, "e")):
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{nm} must be a contiguous float32 CUDA tensor")
+        return _Problem(self.U, self.I, self.m, self.r.data_ptr(), self.e.data_ptr(),
+                        float(self.eps), int(self.T))
+
+
+def _f32(t: torch.Tensor, shape, name):
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {tuple(shape)}")
+
+
+def _optim(rule, lr, beta1, beta2, adam_eps, N, K) -> _Optim:
+    return _Optim(FR_ADAM if rule == "adam" else FR_GD, float(lr), float(beta1), float(beta2),
+                  float(adam_eps), int(N), int(K))
+
+
+def workspace_bytes(prob: Problem, K: int = 1) -> int:
+    n = ctypes.c_size_t()
+    o = _optim("adam", 0.0, 0.9, 0.999, 1e-8, 0, K)
+    p = prob.c()
+    _check(load().fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)),
+           "fr_workspace_bytes")
+    return n.value
+
+
+def step(ctx: Context, prob: Problem, C: torch.Tensor, want_X: bool = False, x_dtype: str = "f32",
+         want_pot: bool = False, sync: bool = True):
+    """fr_step: X = Sinkhorn_T(C), Imp and F.  Returns dict(imp, F, X, pot)."""
+    U, I, m = prob.U, prob.I, prob.m
+    _f32(C, (U, I, m), "C")
+    dev = C.device
+    X = None
+    if want_X:
+        X = torch.empty((U, I, m), dtype=torch.bfloat16 if x_dtype == "bf16" else torch.float32,
+                        device=dev)
+    pot = torch.empty((U, I + m), dtype=torch.float32, device=dev) if want_pot else None
+    imp = torch.empty(I, dtype=torch.float64, device=dev)
+    F = torch.empty(1, dtype=torch.float64, device=dev)
+    nb = workspace_bytes(prob, 1)
+    ws = ctx.workspace(nb)
+    p = prob.c()
+    _check(load().fr_step(ctx.handle, ctypes.byref(p), _ptr(C), _ptr(X),
+                          FR_BF16 if x_dtype == "bf16" else FR_F32, _ptr(pot), _ptr(imp), _ptr(F),
+                          _ptr(ws), ws.numel(), _stream(dev)), "fr_step")
+    if sync:
+        _check(load().fr_sync_status(ctx.handle, _ptr(ws), _stream(dev)), "fr_step (device)")
+    return {"imp": imp, "F": F, "X": X, "pot": pot}
+
+
+def nsw(ctx: Context, prob: Problem, X: torch.Tensor, sync: bool = True):
+    """fr_nsw: Imp and F of a given plan X [U, I, m] (float32 or bfloat16)."""
+    U, I, m = prob.U, prob.I, prob.m
+    if tuple(X.shape) != (U, I, m) or not X.is_contiguous():
+        raise ValueError("X must be contiguous with shape (U, I, m)")
+    if X.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("X must be float32 or bfloat16")
+    imp = torch.empty(I, dtype=torch.float64, device=X.device)
+    F = torch.empty(1, dtype=torch.float64, device=X.device)
+    ws = ctx.workspace(workspace_bytes(prob, 1))
+    p = prob.c()
+    _check(load().fr_nsw(ctx.handle, ctypes.byref(p), _ptr(X),
+                         FR_BF16 if X.dtype == torch.bfloat16 else FR_F32, _ptr(imp), _ptr(F),
+                         _ptr(ws), ws.numel(), _stream(X.device)), "fr_nsw")
+    if sync:
+        _check(load().fr_sync_status(ctx.handle, _ptr(ws), _stream(X.device)), "fr_nsw (device)")
+    return imp, F
+
+
+def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF: float = 1.0,
+             want_dr: bool = True, K: int = 1):
+    """fr_backward: (gF dF/dC, gF dF/dr) through the T unrolled iterations."""
+    U, I, m = prob.U, prob.I, prob.m
+    _f32(C, (U, I, m), "C")
+    if imp.dtype != torch.float64 or imp.numel() != I or not imp.is_cuda:
+        raise ValueError("imp must be a float64 CUDA tensor of length I")
+    imp = imp.contiguous()
+    dC = torch.empty_like(C)
+    dr = torch.empty((U, I), dtype=torch.float32, device=C.device) if want_dr else None
+    ws = ctx.workspace(workspace_bytes(prob, K))
+    p = prob.c()
+    _check(load().fr_backward(ctx.handle, ctypes.byref(p), _ptr(C), _ptr(imp), float(gF), _ptr(dC),
+                              _ptr(dr), int(K), _ptr(ws), ws.numel(), _stream(C.device)),
+           "fr_backward")
+    return dC, dr
+
+
+def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, start_step, K,
+           want_X, x_dtype, plain):
+    U, I, m = prob.U, prob.I, prob.m
+    dev = ctx.device
+    C = torch.zeros((U, I, m), dtype=torch.float32, device=dev) if C0 is None else C0.clone()
+    _f32(C, (U, I, m), "C")
+    if rule == "adam":
+        mom = torch.zeros_like(C) if mom is None else mom.clone()
+        vel = torch.zeros_like(C) if vel is None else vel.clone()
+    else:
+        mom = vel = None
+    X = None
+    if want_X:
+        X = torch.empty((U, I, m), dtype=torch.bfloat16 if x_dtype == "bf16" else torch.float32,
+                        device=dev)
+    Fh = torch.empty(N + 1, dtype=torch.float64, device=dev)
+    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K)
+    p = prob.c()
+    n = ctypes.c_size_t()
+    if plain:
+        _check(load().fr_workspace_bytes_plain(ctypes.byref(p), ctypes.byref(n)),
+               "fr_workspace_bytes_plain")
+    else:
+        _check(load().fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)),
+               "fr_workspace_bytes")
+    ws = ctx.workspace(n.value)
+    _check(fn(ctx.handle, ctypes.byref(p), ctypes.byref(o), _ptr(C), _ptr(mom), _ptr(vel),
+              int(start_step), _ptr(X), FR_BF16 if x_dtype == "bf16" else FR_F32, _ptr(Fh),
+              _ptr(ws), ws.numel(), _stream(dev)), "fr_solve_plain" if plain else "fr_solve")
+    return {"C": C, "X": X, "F_hist": Fh, "mom": mom, "vel": vel}
+
+
+def solve(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,
+          beta2: float = 0.999, adam_eps: float = 1e-8, C0=None, mom=None, vel=None,
+          start_step: int = 0, K: int = 0, want_X: bool = True, x_dtype: str = "f32"):
+    """fr_solve: Algorithm 1 with N ascent steps (captured as a HIP graph)."""
+    return _solve(load().fr_solve, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel,
+                  start_step, K, want_X, x_dtype, False)
+
+
+def solve_plain(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam",
+                beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8, C0=None,
+                mom=None, vel=None, start_step: int = 0, want_X: bool = True,
+                x_dtype: str = "f32"):
+    """fr_solve_plain: the unfused baseline form (one launch per half-iteration)."""
+    return _solve(load().fr_solve_plain, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom,
+                  vel, start_step, 1, want_X, x_dtype, True)
+
+
+# --------------------------------------------------------------------------
+class SinkhornNSW(torch.autograd.Function):
+    """F = sum_i log Imp_i(X_T(C)) as a differentiable function of (C, r).
+
+    forward calls fr_step; backward calls fr_backward, which recomputes the
+    Sinkhorn iterations from C with potentials checkpointed every K."""
+
+    @staticmethod
+    def forward(actx, C, r, e, eps, T, K, fr_ctx):
+        prob = Problem(r.detach().contiguous(), e.detach().contiguous(), float(eps), int(T))
+        out = step(fr_ctx, prob, C.detach().contiguous())
+        actx.save_for_backward(C, out["imp"])
+        actx.prob = prob
+        actx.K = int(K)
+        actx.fr_ctx = fr_ctx
+        return out["F"][0]
+
+    @staticmethod
+    def backward(actx, gF):
+        C, imp = actx.saved_tensors
+        dC, dr = backward(actx.fr_ctx, actx.prob, C.detach().contiguous(), imp, float(gF.item()),
+                          want_dr=actx.needs_input_grad[1], K=actx.K)
+        return dC, dr, None, None, None, None, None
+
+
+def sinkhorn_nsw(C, r, e, eps, T, K=50, ctx: Optional[Context] = None):
+    """Differentiable log-NSW objective of the Sinkhorn plans of C."""
+    ctx = ctx or _default_ctx(C.device)
+    return SinkhornNSW.apply(C, r, e, eps, T, K, ctx)
+
+
+_ctxs = {}
+
+
+def _default_ctx(device) -> Context:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if idx not in _ctxs:
+        _ctxs[idx] = Context(idx)
+    return _ctxs[idx]

@@ -1,0 +1,552 @@
+// fr_api.hip -- host side of the fair-ranking C ABI (include/fairrank.h):
+// argument validation, workspace layout, launch-configuration choice, and
+// the HIP-graph driven outer loop of Algorithm 1.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/fairrank.h"
+#include "fr_internal.h"
+
+using namespace fr;
+
+struct fr_ctx {
+    int device = 0;
+    hipStream_t own = nullptr;                           // used when the caller passes NULL
+    std::map<std::pair<int, int>, std::pair<int, int>> launch;  // (I, m) -> (lanes, rows)
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxItems = 4096;
+constexpr int kMaxM = 64;
+constexpr size_t kMaxLds = 64 * 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+#define FR_TRY(expr)                                  \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return FR_E_DEVICE;     \
+    } while (0)
+
+// ---------------------------------------------------------------- registry
+struct Registry {
+    std::vector<FusedEntry> all;
+    Registry() {
+#define FR_ADD(mp)                                               \
+    {                                                            \
+        int n = 0;                                               \
+        const FusedEntry* p = fused_entries_##mp(&n);            \
+        for (int q = 0; q < n; ++q) all.push_back(p[q]);         \
+    }
+        FR_MP_CLASSES(FR_ADD)
+#undef FR_ADD
+    }
+    int mp_for(int m) const {
+        int best = 1 << 30;
+        for (auto& e : all)
+            if (e.mp >= m && e.mp < best) best = e.mp;
+        return best == (1 << 30) ? -1 : best;
+    }
+    const FusedEntry* find(int mp, int rows, int lb) const {
+        for (auto& e : all)
+            if (e.mp == mp && e.rows == rows && e.lb == lb) return &e;
+        return nullptr;
+    }
+};
+
+const Registry& registry() {
+    static Registry r;
+    return r;
+}
+
+bool lanes_ok(int L) {
+    if (L >= 1 && L <= 64) return (L & (L - 1)) == 0;
+    return L > 64 && L <= 1024 && L % 64 == 0;
+}
+
+// Launch shape of the fused kernels for one problem.
+struct Shape {
+    const FusedEntry* fe;
+    int L, R, mp, block, teams, grid;
+    size_t lds_fwd, lds_bwd;
+};
+
+// Lane-cycle model of one Sinkhorn iteration per consumer: R*MP cells per
+// lane at ~9 issue slots (one quarter-rate exponential plus five full-rate
+// ops) plus the column reduction (log2 L butterfly steps per column, an LDS
+// exchange across waves) and the column update.
+double model_cost(int I, int mp, int L, int R) {
+    (void)I;
+    const double cell = 9.0 * R * mp;
+    const double steps = (double)std::min(6, (int)ceil(log2((double)std::min(L, 64)) - 1e-9));
+    double red = mp * steps;
+    if (L > 64) red += 2.0 * mp + 40.0;
+    double upd = (L >= 64) ? 2.0 * mp + 4.0 : 4.0 * mp;
+    return (double)L * (cell + red + upd);
+}
+
+std::pair<int, int> default_launch(int I, int m) {
+    const Registry& reg = registry();
+    const int mp = reg.mp_for(m);
+    double best = 1e300;
+    std::pair<int, int> out{64, 1};
+    const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 576, 640, 704,
+                      768, 832, 896, 960, 1024};
+    for (int L : Ls) {
+        for (auto& e : reg.all) {
+            if (e.mp != mp) continue;
+            const int R = e.rows;
+            if ((int64_t)L * R < I) continue;
+            if (e.lb == 256 && L > 256) continue;
+            if (e.lb == 1024 && L <= 256) continue;
+            if (R * mp > 64) continue;  // keep the backward's share within registers
+            // no more lanes than rows need
+            if ((int64_t)L * (R - 1) >= I) continue;
+            const double c = model_cost(I, mp, L, R);
+            if (c < best) {
+                best = c;
+                out = {L, R};
+            }
+        }
+    }
+    return out;
+}
+
+fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
+    const Registry& reg = registry();
+    const int mp = reg.mp_for(m);
+    if (mp < 0) return FR_E_UNSUPPORTED;
+    std::pair<int, int> lr;
+    auto it = ctx->launch.find({I, m});
+    lr = (it != ctx->launch.end()) ? it->second : default_launch(I, m);
+    const int L = lr.first, R = lr.second;
+    if (!lanes_ok(L) || (int64_t)L * R < I) return FR_E_PARAM;
+    int block = (L <= 64) ? 256 : L;
+    const int lb = (block <= 256) ? 256 : 1024;
+    const FusedEntry* fe = reg.find(mp, R, lb);
+    if (!fe) return FR_E_UNSUPPORTED;
+    const int W = (L + 63) / 64;
+    const int BL = (K <= 1) ? kLoadBlock : K;
+    auto per_team_bwd = [&](void) { return (size_t)((BL + 1) * mp + 2 * W * mp) * sizeof(float); };
+    int teams = block / L;
+    while (teams > 1 && teams * per_team_bwd() > kMaxLds) {
+        teams /= 2;
+    }
+    if (teams * per_team_bwd() > kMaxLds) return FR_E_UNSUPPORTED;
+    block = teams * L;
+    sh->fe = fe;
+    sh->L = L;
+    sh->R = R;
+    sh->mp = mp;
+    sh->block = block;
+    sh->teams = teams;
+    sh->grid = (int)((U + teams - 1) / teams);
+    sh->lds_fwd = (size_t)teams * 2 * W * mp * sizeof(float);
+    sh->lds_bwd = (size_t)teams * per_team_bwd();
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+struct Layout {
+    size_t hdr, imp, partial, y, hist, total;
+    int nchunk, nck, hs;
+};
+
+int n_checkpoints(int T, int K) { return (T + K - 1) / K + 1; }
+
+Layout layout(const fr_problem* p, int K) {
+    Layout L;
+    const int64_t U = p->n_users;
+    const int I = p->n_items;
+    L.nchunk = impact_chunks(U, I);
+    L.nck = n_checkpoints(p->sinkhorn_iters, K);
+    L.hs = p->m;
+    size_t off = 0;
+    L.hdr = off;
+    off += align_up(sizeof(WsHeader));
+    L.imp = off;
+    off += align_up(sizeof(double) * I);
+    L.partial = off;
+    off += align_up(sizeof(double) * (size_t)L.nchunk * I);
+    L.y = off;
+    off += align_up(sizeof(float) * (size_t)U * I);
+    L.hist = off;
+    off += align_up(sizeof(float) * (size_t)U * L.nck * L.hs);
+    L.total = off;
+    return L;
+}
+
+fr_status check_problem(const fr_problem* p) {
+    if (!p) return FR_E_NULL;
+    if (p->n_users < 1 || p->n_items < 2 || p->n_items > kMaxItems || p->m < 2 ||
+        p->m > p->n_items || p->m > kMaxM)
+        return FR_E_SHAPE;
+    if (!(p->eps > 0.f) || !isfinite(p->eps) || p->sinkhorn_iters < 1) return FR_E_PARAM;
+    if (!p->r || !p->e) return FR_E_NULL;
+    return FR_OK;
+}
+
+int resolve_k(int K) { return K <= 0 ? 1 : K; }
+
+hipStream_t pick_stream(fr_ctx* ctx, void* s) {
+    return s ? (hipStream_t)s : ctx->own;
+}
+
+FwdArgs fwd_args(const fr_problem* p, const Shape& sh, const float* C) {
+    FwdArgs a{};
+    a.C = C;
+    a.r = p->r;
+    a.e = p->e;
+    a.U = p->n_users;
+    a.I = p->n_items;
+    a.m = p->m;
+    a.T = p->sinkhorn_iters;
+    a.K = 1;
+    a.nck = 0;
+    a.hs = p->m;
+    a.L = sh.L;
+    a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
+    a.eps_ln2 = (float)((double)p->eps * M_LN2);
+    return a;
+}
+
+BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
+    BwdArgs a{};
+    a.C = C;
+    a.r = p->r;
+    a.e = p->e;
+    a.U = p->n_users;
+    a.I = p->n_items;
+    a.m = p->m;
+    a.T = p->sinkhorn_iters;
+    a.hs = p->m;
+    a.L = sh.L;
+    a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
+    a.inv_eps = (float)(1.0 / (double)p->eps);
+    a.gF = 1.0;
+    return a;
+}
+
+fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
+    sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status launch_bwd(const Shape& sh, const BwdArgs& a, hipStream_t s) {
+    sh.fe->bwd(a, sh.grid, sh.block, sh.lds_bwd, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+__global__ void k_init_header(WsHeader* h, int64_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        h->flags = 0;
+        h->step = step;
+        for (int q = 0; q < 8; ++q) h->work[q] = 0;
+        h->F = 0.0;
+    }
+}
+
+__global__ void k_set_step(WsHeader* h, int64_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) h->step = step;
+}
+
+fr_status read_flags(WsHeader* h, hipStream_t s, bool clear) {
+    uint32_t fl = 0;
+    FR_TRY(hipMemcpyAsync(&fl, &h->flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    FR_TRY(hipStreamSynchronize(s));
+    if (clear && fl) {
+        uint32_t z = 0;
+        FR_TRY(hipMemcpyAsync(&h->flags, &z, sizeof(z), hipMemcpyHostToDevice, s));
+        FR_TRY(hipStreamSynchronize(s));
+    }
+    if (fl & FLAG_NONFINITE) return FR_E_NONFINITE;
+    if (fl & FLAG_ZERO_IMPACT) return FR_E_ZERO_IMPACT;
+    return FR_OK;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+const char* fr_status_string(fr_status s) {
+    switch (s) {
+        case FR_OK: return "ok";
+        case FR_E_NULL: return "a required pointer is NULL";
+        case FR_E_SHAPE: return "sizes out of range (need 1<=U, 2<=m<=I, I<=4096, m<=64)";
+        case FR_E_PARAM: return "invalid parameter (eps, iteration or step counts, optimiser)";
+        case FR_E_WORKSPACE: return "workspace smaller than fr_workspace_bytes";
+        case FR_E_DEVICE: return "HIP runtime error";
+        case FR_E_NONFINITE: return "non-finite value in impacts or objective";
+        case FR_E_ZERO_IMPACT: return "an item impact is <= 0 (log undefined)";
+        case FR_E_UNSUPPORTED: return "request not supported by this build";
+    }
+    return "unknown status";
+}
+
+fr_status fr_ctx_create(int device, fr_ctx** out) {
+    if (!out) return FR_E_NULL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FR_E_DEVICE;
+    FR_TRY(hipSetDevice(device));
+    fr_ctx* c = new fr_ctx();
+    c->device = device;
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return FR_E_DEVICE;
+    }
+    (void)registry();
+    *out = c;
+    return FR_OK;
+}
+
+void fr_ctx_destroy(fr_ctx* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->own) hipStreamDestroy(ctx->own);
+    delete ctx;
+}
+
+fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size_t* out) {
+    if (!out) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    const int K = optim ? resolve_k(optim->checkpoint_every) : 1;
+    *out = layout(prob, K).total;
+    return FR_OK;
+}
+
+fr_status fr_workspace_init(fr_ctx* ctx, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !ws) return FR_E_NULL;
+    if (ws_bytes < kAlign) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader*)ws, (int64_t)0);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes, int32_t rows) {
+    if (!ctx) return FR_E_NULL;
+    if (n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems) return FR_E_SHAPE;
+    if (!lanes_ok(lanes) || rows < 1 || (int64_t)lanes * rows < n_items) return FR_E_PARAM;
+    const Registry& reg = registry();
+    const int mp = reg.mp_for(m);
+    const int lb = (lanes <= 256) ? 256 : 1024;
+    if (!reg.find(mp, rows, lb)) return FR_E_UNSUPPORTED;
+    ctx->launch[{n_items, m}] = {lanes, rows};
+    return FR_OK;
+}
+
+fr_status fr_get_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t* lanes, int32_t* rows) {
+    if (!ctx || !lanes || !rows) return FR_E_NULL;
+    if (n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems) return FR_E_SHAPE;
+    auto it = ctx->launch.find({n_items, m});
+    std::pair<int, int> lr = (it != ctx->launch.end()) ? it->second : default_launch(n_items, m);
+    *lanes = lr.first;
+    *rows = lr.second;
+    return FR_OK;
+}
+
+fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X, fr_dtype x_dtype,
+                  float* pot, double* imp, double* F, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !ws) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    const Layout Lw = layout(prob, 1);
+    // fr_step needs everything but the history
+    if (ws_bytes < Lw.hist) return FR_E_WORKSPACE;
+    Shape sh;
+    if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, 1, &sh))) return st;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
+    FwdArgs a = fwd_args(prob, sh, C);
+    a.y = (float*)(w + Lw.y);
+    a.X = X;
+    a.x_bf16 = (x_dtype == FR_BF16);
+    a.pot = pot;
+    if ((st = launch_fwd(sh, a, s))) return st;
+    launch_impact(a.y, prob->n_users, prob->n_items, (double*)(w + Lw.partial), Lw.nchunk,
+                  imp ? imp : (double*)(w + Lw.imp), F, nullptr, 0, hdr, 0, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype, double* imp,
+                 double* F, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!X || !ws) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    const Layout Lw = layout(prob, 1);
+    if (ws_bytes < Lw.hist) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    float* y = (float*)(w + Lw.y);
+    launch_rows_from_plan(X, x_dtype == FR_BF16, prob->r, prob->e, prob->n_users, prob->n_items,
+                          prob->m, y, s);
+    launch_impact(y, prob->n_users, prob->n_items, (double*)(w + Lw.partial), Lw.nchunk,
+                  imp ? imp : (double*)(w + Lw.imp), F, nullptr, 0, (WsHeader*)(w + Lw.hdr), 0, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const double* imp,
+                      double gF, float* dC, float* dr, int32_t checkpoint_every, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !imp || !dC || !ws) return FR_E_NULL;
+    if (checkpoint_every < 1 || !isfinite(gF)) return FR_E_PARAM;
+    const int K = checkpoint_every;
+    const Layout Lw = layout(prob, K);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    Shape sh;
+    if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, K, &sh))) return st;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    FwdArgs a = fwd_args(prob, sh, C);
+    a.hist = (float*)(w + Lw.hist);
+    a.K = K;
+    a.nck = Lw.nck;
+    if ((st = launch_fwd(sh, a, s))) return st;
+    BwdArgs b = bwd_args(prob, sh, C);
+    b.hist = a.hist;
+    b.K = K;
+    b.nck = Lw.nck;
+    b.imp = imp;
+    b.gF = gF;
+    b.dC = dC;
+    b.dr = dr;
+    return launch_bwd(sh, b, s);
+}
+
+fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, float* C,
+                   float* adam_m, float* adam_v, int64_t start_step, void* X_out, fr_dtype x_dtype,
+                   double* F_hist, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !optim) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !F_hist || !ws) return FR_E_NULL;
+    if (optim->rule != FR_ADAM && optim->rule != FR_GD) return FR_E_PARAM;
+    if (optim->rule == FR_ADAM && (!adam_m || !adam_v)) return FR_E_NULL;
+    if (optim->outer_steps < 0 || start_step < 0 || !isfinite(optim->lr) || optim->lr < 0.f)
+        return FR_E_PARAM;
+    if (optim->rule == FR_ADAM &&
+        (!(optim->beta1 >= 0.f && optim->beta1 < 1.f) || !(optim->beta2 >= 0.f && optim->beta2 < 1.f) ||
+         !(optim->adam_eps >= 0.f)))
+        return FR_E_PARAM;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    const int K = resolve_k(optim->checkpoint_every);
+    const Layout Lw = layout(prob, K);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    Shape sh;
+    if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, K, &sh))) return st;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
+    char* w = (char*)ws;
+    WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
+    double* imp = (double*)(w + Lw.imp);
+    double* partial = (double*)(w + Lw.partial);
+    float* y = (float*)(w + Lw.y);
+    float* hist = (float*)(w + Lw.hist);
+
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, hdr, start_step);
+    FR_TRY(hipGetLastError());
+
+    FwdArgs a = fwd_args(prob, sh, C);
+    a.y = y;
+    a.hist = hist;
+    a.K = K;
+    a.nck = Lw.nck;
+    BwdArgs b = bwd_args(prob, sh, C);
+    b.hist = hist;
+    b.K = K;
+    b.nck = Lw.nck;
+    b.imp = imp;
+    b.Cw = C;
+    b.mom = adam_m;
+    b.vel = adam_v;
+    b.step_ptr = &hdr->step;
+    b.rule = optim->rule;
+    b.lr = optim->lr;
+    b.b1 = optim->beta1;
+    b.b2 = optim->beta2;
+    b.aeps = optim->adam_eps;
+
+    const int N = optim->outer_steps;
+    if (N > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        FR_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+        launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
+                      start_step, hdr, 1, s);
+        sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (ce != hipSuccess) return FR_E_DEVICE;
+        ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ce != hipSuccess) {
+            hipGraphDestroy(graph);
+            return FR_E_DEVICE;
+        }
+        for (int n = 0; n < N && ce == hipSuccess; ++n) ce = hipGraphLaunch(exec, s);
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        if (ce != hipSuccess) return FR_E_DEVICE;
+    }
+    // final forward: X(C_N) and F_N
+    a.hist = nullptr;
+    a.X = X_out;
+    a.x_bf16 = (x_dtype == FR_BF16);
+    if ((st = launch_fwd(sh, a, s))) return st;
+    launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
+                  start_step, hdr, 0, s);
+    FR_TRY(hipGetLastError());
+    return read_flags(hdr, s, false);
+}
+
+fr_status fr_sync_status(fr_ctx* ctx, void* ws, void* stream) {
+    if (!ctx || !ws) return FR_E_NULL;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    FR_TRY(hipStreamSynchronize(s));
+    return read_flags((WsHeader*)ws, s, true);
+}
+
+fr_status fr_solve_plain(fr_ctx*, const fr_problem*, const fr_optim*, float*, float*, float*,
+                         int64_t, void*, fr_dtype, double*, void*, size_t, void*) {
+    return FR_E_UNSUPPORTED;
+}
+
+fr_status fr_workspace_bytes_plain(const fr_problem* prob, size_t* out) {
+    if (!out) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    *out = 0;
+    return FR_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// fr_internal.h -- structures shared by the HIP kernels and the host side of
+// the fair-ranking library.  Not part of the public ABI (see fairrank.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fr {
+
+// Device-side flag bits written into the workspace header.
+enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_ZERO_IMPACT = 2u };
+
+// Workspace header (first 256 bytes of every workspace).
+struct WsHeader {
+    uint32_t flags;       // FLAG_* bits, sticky until fr_sync_status clears them
+    uint32_t pad0;
+    int64_t step;         // Adam step counter advanced once per outer step
+    uint32_t work[8];     // work-queue counters of the batched kernels
+    double F;             // last objective value
+};
+
+// ---------------------------------------------------------------------------
+// Fused forward: one team of L lanes per consumer, R plan rows per lane held
+// in registers, MP (>= m) columns per row.
+struct FwdArgs {
+    const float* C;        // [U][I][m]
+    const float* r;        // [U][I]
+    const float* e;        // [m-1]
+    float* y;              // [U][I]  r_ui * sum_{k<m-1} e_k x_uik  (or null)
+    float* hist;           // [U][nck][hs] base-2 column potentials (or null)
+    void* X;               // [U][I][m] plan (or null)
+    float* pot;            // [U][I+m] potentials in cost units (or null)
+    int64_t U;
+    int I, m, T, K, nck, hs, L, x_bf16;
+    float c2;              // -1 / (eps ln 2): exponent scale of a cost
+    float eps_ln2;         // eps ln 2: base-2 potential -> cost units
+};
+
+struct BwdArgs {
+    const float* C;        // [U][I][m] cost (read)
+    const float* r;        // [U][I]
+    const float* e;        // [m-1]
+    const float* hist;     // [U][nck][hs] checkpoints written by the forward
+    const double* imp;     // [I]
+    float* dC;             // [U][I][m] gF * dF/dC (or null)
+    float* dr;             // [U][I] gF * dF/dr (or null)
+    float* Cw;             // cost to update in place (or null)
+    float* mom;            // Adam first moment (or null)
+    float* vel;            // Adam second moment (or null)
+    const int64_t* step_ptr;  // device Adam step counter (or null: use step_const)
+    int64_t step_const;
+    double gF;
+    int64_t U;
+    int I, m, T, K, nck, hs, L, rule;
+    float c2, inv_eps, lr, b1, b2, aeps;
+};
+
+typedef void (*FwdLaunch)(const FwdArgs&, int grid, int block, size_t lds, hipStream_t);
+typedef void (*BwdLaunch)(const BwdArgs&, int grid, int block, size_t lds, hipStream_t);
+
+struct FusedEntry {
+    int mp, rows, lb;   // padded columns, rows per lane, launch bound (max block)
+    FwdLaunch fwd;
+    BwdLaunch bwd;
+};
+
+// Instantiated column classes.  Each class is compiled in its own translation
+// unit (fr_fused.hip with -DFR_MP=<mp>).
+#define FR_MP_CLASSES(X) X(5) X(8) X(10) X(11) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(50) X(64)
+#define FR_DECL_ENTRIES(mp) const FusedEntry* fused_entries_##mp(int* n);
+FR_MP_CLASSES(FR_DECL_ENTRIES)
+#undef FR_DECL_ENTRIES
+
+// Reverse-sweep block length when every iterate is kept (K == 1).
+constexpr int kLoadBlock = 32;
+
+// Reductions over consumers (fr_reduce.hip).
+void launch_impact(const float* y, int64_t U, int I, double* partial, int nchunk, double* imp,
+                   double* F, double* F_hist, int64_t start_step, WsHeader* hdr, int advance,
+                   hipStream_t s);
+void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const float* e, int64_t U,
+                           int I, int m, float* y, hipStream_t s);
+int impact_chunks(int64_t U, int I);
+
+}  // namespace fr

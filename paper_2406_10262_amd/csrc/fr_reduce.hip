@@ -1,0 +1,107 @@
+// fr_reduce.hip -- the only cross-consumer step of the method: item impacts
+// Imp_i = sum_u y_ui (Eq. Imp, with y_ui = r_ui sum_{k<m} e_k x_uik formed by
+// the producing kernel) and the objective F = sum_i log Imp_i (Eq. objF).
+//
+// Both sums run in FP64 in a fixed order (consumer chunks, then chunks in
+// index order, then a fixed tree over items), so results are bitwise
+// reproducible from run to run.  Imp_i <= 0 or a non-finite value raises a
+// sticky flag in the workspace header instead of failing the launch.
+#include <math.h>
+
+#include "fr_device.h"
+#include "fr_internal.h"
+
+namespace fr {
+namespace {
+
+constexpr int kChunk = 128;      // consumers per partial sum
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(256) void k_imp_partial(const float* __restrict__ y, int64_t U, int I,
+                                                     double* __restrict__ partial) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch = blockIdx.y;
+    if (i >= I) return;
+    const int64_t u0 = (int64_t)ch * kChunk;
+    const int64_t u1 = min(U, u0 + kChunk);
+    double s = 0.0;
+    for (int64_t u = u0; u < u1; ++u) s += (double)y[u * I + i];
+    partial[(int64_t)ch * I + i] = s;
+}
+
+__global__ __launch_bounds__(kFinalThreads) void k_imp_final(const double* __restrict__ partial,
+                                                             int nchunk, int I, double* imp,
+                                                             double* F, double* F_hist,
+                                                             int64_t start_step, WsHeader* hdr,
+                                                             int advance) {
+    __shared__ double red[kFinalThreads];
+    double lsum = 0.0;
+    uint32_t fl = 0;
+    for (int i = threadIdx.x; i < I; i += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * I + i];
+        if (imp) imp[i] = s;
+        if (!isfinite(s))
+            fl |= FLAG_NONFINITE;
+        else if (!(s > 0.0))
+            fl |= FLAG_ZERO_IMPACT;
+        lsum += log(s);
+    }
+    if (fl) atomicOr(&hdr->flags, fl);
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double Fv = red[0];
+        hdr->F = Fv;
+        if (F) *F = Fv;
+        const int64_t st = hdr->step;
+        if (F_hist) F_hist[st - start_step] = Fv;
+        if (advance) hdr->step = st + 1;
+    }
+}
+
+// y_ui = r_ui sum_{k<m-1} e_k x_uik for an explicit plan (one thread per row).
+__global__ __launch_bounds__(256) void k_rows_from_plan(const void* X, int bf16, const float* r,
+                                                        const float* e, int64_t rows, int m,
+                                                        float* y) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    float s = 0.f;
+    if (bf16) {
+        const uint16_t* x = (const uint16_t*)X + row * m;
+        for (int k = 0; k < m - 1; ++k) s = fmaf(e[k], from_bf16(x[k]), s);
+    } else {
+        const float* x = (const float*)X + row * m;
+        for (int k = 0; k < m - 1; ++k) s = fmaf(e[k], x[k], s);
+    }
+    y[row] = r[row] * s;
+}
+
+}  // namespace
+
+int impact_chunks(int64_t U, int I) {
+    (void)I;
+    return (int)((U + kChunk - 1) / kChunk);
+}
+
+void launch_impact(const float* y, int64_t U, int I, double* partial, int nchunk, double* imp,
+                   double* F, double* F_hist, int64_t start_step, WsHeader* hdr, int advance,
+                   hipStream_t s) {
+    dim3 g1((I + 255) / 256, nchunk);
+    hipLaunchKernelGGL(k_imp_partial, g1, dim3(256), 0, s, y, U, I, partial);
+    hipLaunchKernelGGL(k_imp_final, dim3(1), dim3(kFinalThreads), 0, s, partial, nchunk, I, imp, F,
+                       F_hist, start_step, hdr, advance);
+}
+
+void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const float* e, int64_t U,
+                           int I, int m, float* y, hipStream_t s) {
+    const int64_t rows = U * I;
+    hipLaunchKernelGGL(k_rows_from_plan, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, X,
+                       x_bf16, r, e, rows, m, y);
+}
+
+}  // namespace fr

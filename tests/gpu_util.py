@@ -1,0 +1,38 @@
+"""Helpers shared by the GPU parity tests: device copies of seeded workloads
+and the oracle's results on the identical float32 inputs."""
+import numpy as np
+import torch
+
+import oracle
+
+# Tolerances of the FP32 GPU path against the FP64 oracle.
+X_ABS = 1e-5          # plan entries, FP32 storage
+F_REL = 1e-6          # objective F = sum_i log Imp_i
+IMP_REL = 1e-6        # every item impact
+GRAD_REL = 1e-4       # max |dC - dC_ref| <= GRAD_REL * max |dC_ref|
+
+
+def device_problem(fr, r: np.ndarray, e: np.ndarray, eps, T: int):
+    return fr.Problem(torch.from_numpy(np.ascontiguousarray(r)).cuda(),
+                      torch.from_numpy(np.ascontiguousarray(e)).cuda(), float(eps), int(T))
+
+
+def oracle_step(r, e, eps, T, C):
+    X = oracle.forward(C, float(eps), T)
+    imp = oracle.impact(r, e, X)
+    return X, imp, oracle.nsw(imp)
+
+
+def rel(a, b):
+    return abs(float(a) - float(b)) / max(abs(float(b)), 1e-300)
+
+
+def assert_step_close(out, X_ref, imp_ref, F_ref, x_abs=X_ABS):
+    imp = out["imp"].cpu().numpy()
+    F = float(out["F"].cpu()[0])
+    assert np.max(np.abs(imp / imp_ref - 1)) <= IMP_REL, np.max(np.abs(imp / imp_ref - 1))
+    assert rel(F, F_ref) <= F_REL, (F, F_ref)
+    if out.get("X") is not None:
+        X = out["X"].float().cpu().numpy()
+        err = np.max(np.abs(X - X_ref))
+        assert err <= x_abs, err
