@@ -1,0 +1,44 @@
+/*
+ * fairrank_diag.h -- diagnostics of libfairrank: per-kernel timing of the
+ * fused solver and microbenchmarks of the device ceilings it is measured
+ * against.  Not needed to use the solver (include/fairrank.h).
+ */
+#ifndef FAIRRANK_DIAG_H
+#define FAIRRANK_DIAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fairrank.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Kernel timing.  While enabled, fr_solve launches its kernels directly
+ * (no graph) and brackets every fused forward and backward launch with HIP
+ * events on the call's stream.  fr_ctx_kernel_times returns the milliseconds
+ * and launch counts accumulated since timing was last enabled (host
+ * pointers, each optional). */
+fr_status fr_ctx_set_timing(fr_ctx* ctx, int enable);
+fr_status fr_ctx_kernel_times(fr_ctx* ctx, double* fwd_ms, int64_t* fwd_launches,
+                              double* bwd_ms, int64_t* bwd_launches);
+
+/* ALU microbenchmark on the current device, default stream, synchronous:
+ * kind 0 = dependent chains of v_exp_f32, 1 = chains of FP32 FMA, 2 = one
+ * exponential followed by five FMAs.  `blocks` blocks of 256 threads, each
+ * lane running `iters` steps on 8 independent chains.  *ms_out = kernel time,
+ * *ops_out = lane-steps executed (exps, FMAs, or exp+5 FMA groups). */
+fr_status fr_diag_alu(int kind, int blocks, int iters, double* ms_out, double* ops_out);
+
+/* HBM copy of `bytes` (multiple of 16) from src to dst (device), `reps`
+ * timed repetitions after one warm-up on `stream`; *ms_out = mean time per
+ * copy.  Moves 2 * bytes per repetition; its profiler byte counts calibrate
+ * those of the solver's kernels. */
+fr_status fr_diag_copy(const void* src, void* dst, size_t bytes, int reps, double* ms_out,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAIRRANK_DIAG_H */

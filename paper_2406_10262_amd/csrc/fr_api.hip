@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/fairrank.h"
+#include "../../include/fairrank_diag.h"
 #include "fr_internal.h"
 
 using namespace fr;
@@ -21,6 +22,9 @@ struct fr_ctx {
     int device = 0;
     hipStream_t own = nullptr;                           // used when the caller passes NULL
     std::map<std::pair<int, int>, std::pair<int, int>> launch;  // (I, m) -> (lanes, rows)
+    bool timing = false;                                  // per-kernel event timing
+    double fwd_ms = 0.0, bwd_ms = 0.0;
+    int64_t fwd_n = 0, bwd_n = 0;
 };
 
 namespace {
@@ -197,6 +201,47 @@ fr_status check_problem(const fr_problem* p) {
 }
 
 int resolve_k(int K) { return K <= 0 ? 1 : K; }
+
+struct PlainLayout {
+    size_t hdr, imp, partial, y, fh, gh, cbar, fbar, fbar0, gbar, total;
+    int nchunk;
+};
+
+PlainLayout plain_layout(const fr_problem* p) {
+    PlainLayout L;
+    const int64_t U = p->n_users;
+    const int I = p->n_items, m = p->m, T = p->sinkhorn_iters;
+    L.nchunk = impact_chunks(U, I);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    L.hdr = take(sizeof(WsHeader));
+    L.imp = take(sizeof(double) * I);
+    L.partial = take(sizeof(double) * (size_t)L.nchunk * I);
+    L.y = take(sizeof(float) * (size_t)U * I);
+    L.fh = take(sizeof(float) * (size_t)T * U * I);
+    L.gh = take(sizeof(float) * (size_t)(T + 1) * U * m);
+    L.cbar = take(sizeof(float) * (size_t)U * I * m);
+    L.fbar = take(sizeof(float) * (size_t)U * I);
+    L.fbar0 = take(sizeof(float) * (size_t)U * I);
+    L.gbar = take(sizeof(float) * (size_t)U * m);
+    L.total = off;
+    return L;
+}
+
+fr_status check_optim(const fr_optim* o, const float* mom, const float* vel, int64_t start_step) {
+    if (o->rule != FR_ADAM && o->rule != FR_GD) return FR_E_PARAM;
+    if (o->rule == FR_ADAM && (!mom || !vel)) return FR_E_NULL;
+    if (o->outer_steps < 0 || start_step < 0 || !isfinite(o->lr) || o->lr < 0.f) return FR_E_PARAM;
+    if (o->rule == FR_ADAM &&
+        (!(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f) ||
+         !(o->adam_eps >= 0.f)))
+        return FR_E_PARAM;
+    return FR_OK;
+}
 
 hipStream_t pick_stream(fr_ctx* ctx, void* s) {
     return s ? (hipStream_t)s : ctx->own;
@@ -448,15 +493,8 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     if (!ctx || !optim) return FR_E_NULL;
     fr_status st = check_problem(prob);
     if (st) return st;
+    if ((st = check_optim(optim, adam_m, adam_v, start_step))) return st;
     if (!C || !F_hist || !ws) return FR_E_NULL;
-    if (optim->rule != FR_ADAM && optim->rule != FR_GD) return FR_E_PARAM;
-    if (optim->rule == FR_ADAM && (!adam_m || !adam_v)) return FR_E_NULL;
-    if (optim->outer_steps < 0 || start_step < 0 || !isfinite(optim->lr) || optim->lr < 0.f)
-        return FR_E_PARAM;
-    if (optim->rule == FR_ADAM &&
-        (!(optim->beta1 >= 0.f && optim->beta1 < 1.f) || !(optim->beta2 >= 0.f && optim->beta2 < 1.f) ||
-         !(optim->adam_eps >= 0.f)))
-        return FR_E_PARAM;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
     const int K = resolve_k(optim->checkpoint_every);
     const Layout Lw = layout(prob, K);
@@ -497,7 +535,33 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     b.aeps = optim->adam_eps;
 
     const int N = optim->outer_steps;
-    if (N > 0) {
+    if (N > 0 && ctx->timing) {
+        // direct launches, each fused kernel bracketed by events
+        std::vector<hipEvent_t> ev(4 * (size_t)N);
+        for (auto& x : ev) FR_TRY(hipEventCreate(&x));
+        for (int n = 0; n < N; ++n) {
+            FR_TRY(hipEventRecord(ev[4 * n + 0], s));
+            sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+            FR_TRY(hipEventRecord(ev[4 * n + 1], s));
+            launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
+                          start_step, hdr, 1, s);
+            FR_TRY(hipEventRecord(ev[4 * n + 2], s));
+            sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+            FR_TRY(hipEventRecord(ev[4 * n + 3], s));
+        }
+        FR_TRY(hipGetLastError());
+        FR_TRY(hipStreamSynchronize(s));
+        for (int n = 0; n < N; ++n) {
+            float t1 = 0.f, t2 = 0.f;
+            FR_TRY(hipEventElapsedTime(&t1, ev[4 * n + 0], ev[4 * n + 1]));
+            FR_TRY(hipEventElapsedTime(&t2, ev[4 * n + 2], ev[4 * n + 3]));
+            ctx->fwd_ms += t1;
+            ctx->bwd_ms += t2;
+        }
+        ctx->fwd_n += N;
+        ctx->bwd_n += N;
+        for (auto& x : ev) hipEventDestroy(x);
+    } else if (N > 0) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         FR_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -528,6 +592,24 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     return read_flags(hdr, s, false);
 }
 
+fr_status fr_ctx_set_timing(fr_ctx* ctx, int enable) {
+    if (!ctx) return FR_E_NULL;
+    ctx->timing = enable != 0;
+    ctx->fwd_ms = ctx->bwd_ms = 0.0;
+    ctx->fwd_n = ctx->bwd_n = 0;
+    return FR_OK;
+}
+
+fr_status fr_ctx_kernel_times(fr_ctx* ctx, double* fwd_ms, int64_t* fwd_launches, double* bwd_ms,
+                              int64_t* bwd_launches) {
+    if (!ctx) return FR_E_NULL;
+    if (fwd_ms) *fwd_ms = ctx->fwd_ms;
+    if (fwd_launches) *fwd_launches = ctx->fwd_n;
+    if (bwd_ms) *bwd_ms = ctx->bwd_ms;
+    if (bwd_launches) *bwd_launches = ctx->bwd_n;
+    return FR_OK;
+}
+
 fr_status fr_sync_status(fr_ctx* ctx, void* ws, void* stream) {
     if (!ctx || !ws) return FR_E_NULL;
     FR_TRY(hipSetDevice(ctx->device));
@@ -536,17 +618,58 @@ fr_status fr_sync_status(fr_ctx* ctx, void* ws, void* stream) {
     return read_flags((WsHeader*)ws, s, true);
 }
 
-fr_status fr_solve_plain(fr_ctx*, const fr_problem*, const fr_optim*, float*, float*, float*,
-                         int64_t, void*, fr_dtype, double*, void*, size_t, void*) {
-    return FR_E_UNSUPPORTED;
-}
-
 fr_status fr_workspace_bytes_plain(const fr_problem* prob, size_t* out) {
     if (!out) return FR_E_NULL;
     fr_status st = check_problem(prob);
     if (st) return st;
-    *out = 0;
-    return FR_E_UNSUPPORTED;
+    *out = plain_layout(prob).total;
+    return FR_OK;
+}
+
+fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, float* C,
+                         float* adam_m, float* adam_v, int64_t start_step, void* X_out,
+                         fr_dtype x_dtype, double* F_hist, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!ctx || !optim) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if ((st = check_optim(optim, adam_m, adam_v, start_step))) return st;
+    if (!C || !F_hist || !ws) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    const PlainLayout Lw = plain_layout(prob);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
+    char* w = (char*)ws;
+    PlainBufs b;
+    b.hdr = (WsHeader*)(w + Lw.hdr);
+    b.imp = (double*)(w + Lw.imp);
+    b.partial = (double*)(w + Lw.partial);
+    b.y = (float*)(w + Lw.y);
+    b.fh = (float*)(w + Lw.fh);
+    b.gh = (float*)(w + Lw.gh);
+    b.cbar = (float*)(w + Lw.cbar);
+    b.fbar = (float*)(w + Lw.fbar);
+    b.fbar0 = (float*)(w + Lw.fbar0);
+    b.gbar = (float*)(w + Lw.gbar);
+    b.nchunk = Lw.nchunk;
+    const int64_t U = prob->n_users;
+    const int I = prob->n_items, m = prob->m, T = prob->sinkhorn_iters;
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, b.hdr, start_step);
+    for (int n = 0; n < optim->outer_steps; ++n) {
+        plain_forward(C, prob->r, prob->e, U, I, m, prob->eps, T, b, nullptr, 0, s);
+        launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr, 1,
+                      s);
+        plain_backward_update(C, prob->r, prob->e, U, I, m, prob->eps, T, b, adam_m, adam_v,
+                              optim->rule, optim->lr, optim->beta1, optim->beta2, optim->adam_eps,
+                              s);
+        FR_TRY(hipGetLastError());
+    }
+    plain_forward(C, prob->r, prob->e, U, I, m, prob->eps, T, b, X_out, x_dtype == FR_BF16, s);
+    launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr, 0, s);
+    FR_TRY(hipGetLastError());
+    return read_flags(b.hdr, s, false);
 }
 
 }  // extern "C"

@@ -81,4 +81,17 @@ void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const floa
                            int I, int m, float* y, hipStream_t s);
 int impact_chunks(int64_t U, int I);
 
+// Unfused baseline form (fr_plain.hip).
+struct PlainBufs {
+    float *fh, *gh, *y, *cbar, *fbar, *fbar0, *gbar;
+    double *imp, *partial;
+    WsHeader* hdr;
+    int nchunk;
+};
+void plain_forward(const float* C, const float* r, const float* e, int64_t U, int I, int m,
+                   float eps, int T, const PlainBufs& b, void* X, int bf16, hipStream_t s);
+void plain_backward_update(float* C, const float* r, const float* e, int64_t U, int I, int m,
+                           float eps, int T, const PlainBufs& b, float* mom, float* vel, int rule,
+                           float lr, float b1, float b2, float aeps, hipStream_t s);
+
 }  // namespace fr

@@ -103,3 +103,50 @@ def test_solve_resume_matches_single_run(fr, ctx):
     assert torch.equal(b["C"], full["C"])
     assert torch.equal(b["F_hist"], full["F_hist"][2:])
     assert torch.equal(a["F_hist"], full["F_hist"][:3])
+
+
+def test_plain_form_matches_oracle_and_fused(fr, ctx):
+    inst = W.config("C1")
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    res = fr.solve_plain(ctx, prob, 10, float(inst.lr))
+    ref = oracle.solve(inst.r, inst.e, float(inst.eps), inst.T, 10, lr=float(inst.lr))
+    Fh = res["F_hist"].cpu().numpy()
+    assert np.max(np.abs(Fh / ref["F_hist"] - 1)) <= F_REL
+    assert np.max(np.abs(res["X"].double().cpu().numpy() - ref["X"])) <= 1e-5
+    fused = fr.solve(ctx, prob, 10, float(inst.lr))
+    assert np.max(np.abs(fused["F_hist"].cpu().numpy() / Fh - 1)) <= F_REL
+
+
+def test_solve_timing_mode_matches_graph_mode(fr, ctx):
+    import ctypes
+    inst = W.config("C1")
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    lib = fr.load()
+    lib.fr_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    g = fr.solve(ctx, prob, 5, float(inst.lr))
+    lib.fr_ctx_set_timing(ctx.handle, 1)
+    t = fr.solve(ctx, prob, 5, float(inst.lr))
+    lib.fr_ctx_set_timing(ctx.handle, 0)
+    assert torch.equal(g["C"], t["C"]) and torch.equal(g["F_hist"], t["F_hist"])
+
+
+def test_solve_C2_matches_oracle_trajectory(fr, ctx):
+    """2000 x 100 x 10, T=200, N=100 Adam steps against the stored FP64
+    oracle trajectory (tests/golden/c2_trajectory.json)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2_trajectory.json")) as fh:
+        gold = json.load(fh)
+    inst = W.config("C2")
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    res = fr.solve(ctx, prob, inst.N, float(inst.lr))
+    Fh = res["F_hist"].cpu().numpy()
+    ref = np.array(gold["F_hist"])
+    err = np.max(np.abs(Fh / ref - 1))
+    print("C2 trajectory F rel err", err, flush=True)
+    assert err <= F_REL
+    imp_ref = np.array(gold["imp_final"])
+    prob_out = fr.nsw(ctx, prob, res["X"])
+    imp = prob_out[0].cpu().numpy()
+    print("C2 final impacts rel err", np.max(np.abs(imp / imp_ref - 1)), flush=True)
+    assert np.max(np.abs(imp / imp_ref - 1)) <= 1e-5
