@@ -128,18 +128,12 @@ __device__ __forceinline__ void row_step(const float (&c)[R][MP], const float (&
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float z[MP];
-        float M = kNeg;
 #pragma unroll
-        for (int k = 0; k < MP; ++k) {
-            z[k] = fmaf(c[j][k], c2, gam[k]);
-            M = fmaxf(M, z[k]);
-        }
-        float s = 0.f;
+        for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], c2, gam[k]);
+        const float M = Tree<MP>::max(z);
 #pragma unroll
-        for (int k = 0; k < MP; ++k) {
-            z[k] = ex2(z[k] - M);
-            s += z[k];
-        }
+        for (int k = 0; k < MP; ++k) z[k] = ex2(z[k] - M);
+        const float s = Tree<MP>::sum(z);
         const float w = om[j] * rcp(s);
 #pragma unroll
         for (int k = 0; k < MP; ++k) acc[k] = fmaf(z[k], w, acc[k]);
@@ -329,19 +323,12 @@ __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     float z[MP];
-                    float M = kNeg;
 #pragma unroll
-                    for (int k = 0; k < MP; ++k) {
-                        z[k] = fmaf(c[j][k], a.c2, gp[k]);
-                        M = fmaxf(M, z[k]);
-                    }
-                    float sum = 0.f;
+                    for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], a.c2, gp[k]);
+                    const float M = Tree<MP>::max(z);
 #pragma unroll
-                    for (int k = 0; k < MP; ++k) {
-                        z[k] = ex2(z[k] - M);
-                        sum += z[k];
-                    }
-                    const float w = om[j] * rcp(sum);
+                    for (int k = 0; k < MP; ++k) z[k] = ex2(z[k] - M);
+                    const float w = om[j] * rcp(Tree<MP>::sum(z));
                     float gsum = 0.f, xe = 0.f;
 #pragma unroll
                     for (int k = 0; k < MP; ++k) {
@@ -376,21 +363,17 @@ __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
             for (int k = 0; k < MP; ++k) acc[k] = 0.f;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                float z[MP];
-                float M = kNeg;
+                float z[MP], zg[MP];
 #pragma unroll
-                for (int k = 0; k < MP; ++k) {
-                    z[k] = fmaf(c[j][k], a.c2, gp[k]);
-                    M = fmaxf(M, z[k]);
-                }
-                float sum = 0.f, d = 0.f;
+                for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], a.c2, gp[k]);
+                const float M = Tree<MP>::max(z);
 #pragma unroll
                 for (int k = 0; k < MP; ++k) {
                     z[k] = ex2(z[k] - M);
-                    sum += z[k];
-                    d = fmaf(z[k], gh[k], d);
+                    zg[k] = z[k] * gh[k];
                 }
-                const float w = om[j] * rcp(sum);
+                const float w = om[j] * rcp(Tree<MP>::sum(z));
+                const float d = Tree<MP>::sum(zg);
                 const float fb = (t == a.T ? fb0[j] : 0.f) - w * d;
                 const float aa = w * fb;
 #pragma unroll

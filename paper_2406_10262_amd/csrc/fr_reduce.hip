@@ -14,23 +14,48 @@
 namespace fr {
 namespace {
 
-constexpr int kChunk = 128;      // consumers per partial sum
+constexpr int kChunk = 16;       // consumers per first-stage partial sum
+constexpr int kItemLanes = 32;   // lanes summing one item's partials
 constexpr int kFinalThreads = 1024;
 
+// Stage 1: partial[ch][i] = sum of y[u][i] over the 16 consumers of chunk ch
+// (independent loads, added in consumer order).
 __global__ __launch_bounds__(256) void k_imp_partial(const float* __restrict__ y, int64_t U, int I,
                                                      double* __restrict__ partial) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ch = blockIdx.y;
+    const int64_t ch = blockIdx.y;
     if (i >= I) return;
-    const int64_t u0 = (int64_t)ch * kChunk;
-    const int64_t u1 = min(U, u0 + kChunk);
+    const int64_t u0 = ch * kChunk;
+    float v[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) v[q] = (u0 + q < U) ? y[(u0 + q) * I + i] : 0.f;
     double s = 0.0;
-    for (int64_t u = u0; u < u1; ++u) s += (double)y[u * I + i];
-    partial[(int64_t)ch * I + i] = s;
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) s += (double)v[q];
+    partial[ch * I + i] = s;
 }
 
-__global__ __launch_bounds__(kFinalThreads) void k_imp_final(const double* __restrict__ partial,
-                                                             int nchunk, int I, double* imp,
+// Stage 2: Imp_i = sum over chunks; 32 lanes per item take chunks c = lane
+// mod 32 in order, then a fixed tree combines the lanes.
+__global__ __launch_bounds__(256) void k_imp_items(const double* __restrict__ partial, int nchunk,
+                                                   int I, double* __restrict__ imp) {
+    __shared__ double red[256];
+    const int lane = threadIdx.x % kItemLanes;
+    const int i = blockIdx.x * (256 / kItemLanes) + threadIdx.x / kItemLanes;
+    double s = 0.0;
+    if (i < I)
+        for (int c = lane; c < nchunk; c += kItemLanes) s += partial[(int64_t)c * I + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kItemLanes / 2; w > 0; w >>= 1) {
+        if (lane < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (i < I && lane == 0) imp[i] = red[threadIdx.x];
+}
+
+// Stage 3: F = sum_i log Imp_i (fixed tree), device flags, F history, step.
+__global__ __launch_bounds__(kFinalThreads) void k_imp_final(const double* __restrict__ imp, int I,
                                                              double* F, double* F_hist,
                                                              int64_t start_step, WsHeader* hdr,
                                                              int advance) {
@@ -38,9 +63,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_imp_final(const double* __res
     double lsum = 0.0;
     uint32_t fl = 0;
     for (int i = threadIdx.x; i < I; i += blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * I + i];
-        if (imp) imp[i] = s;
+        const double s = imp[i];
         if (!isfinite(s))
             fl |= FLAG_NONFINITE;
         else if (!(s > 0.0))
@@ -93,8 +116,9 @@ void launch_impact(const float* y, int64_t U, int I, double* partial, int nchunk
                    hipStream_t s) {
     dim3 g1((I + 255) / 256, nchunk);
     hipLaunchKernelGGL(k_imp_partial, g1, dim3(256), 0, s, y, U, I, partial);
-    hipLaunchKernelGGL(k_imp_final, dim3(1), dim3(kFinalThreads), 0, s, partial, nchunk, I, imp, F,
-                       F_hist, start_step, hdr, advance);
+    hipLaunchKernelGGL(k_imp_items, dim3((I + 7) / 8), dim3(256), 0, s, partial, nchunk, I, imp);
+    hipLaunchKernelGGL(k_imp_final, dim3(1), dim3(kFinalThreads), 0, s, imp, I, F, F_hist,
+                       start_step, hdr, advance);
 }
 
 void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const float* e, int64_t U,
