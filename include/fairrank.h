@@ -26,8 +26,11 @@
  *     A context owns only its launch-configuration (autotune) cache and its
  *     captured graphs.
  *   * All calls are asynchronous on the given stream (a hipStream_t passed
- *     as void*; NULL = the default stream) unless documented otherwise.  A
- *     context must not be used from two host threads at once.
+ *     as void*; NULL = the null stream) unless documented otherwise.
+ *     fr_solve and fr_solve_plain return synchronised; given NULL they wait
+ *     for the null stream, run on a stream of the context (a graph cannot be
+ *     captured on the null stream) and wait for it.  A context must not be
+ *     used from two host threads at once.
  *   * Every call returns an fr_status and never aborts.  Argument errors are
  *     detected on the host and returned before anything is enqueued.
  *     Conditions found on the device (a non-finite value, an impact <= 0) set

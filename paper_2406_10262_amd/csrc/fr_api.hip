@@ -243,9 +243,13 @@ fr_status check_optim(const fr_optim* o, const float* mom, const float* vel, int
     return FR_OK;
 }
 
-hipStream_t pick_stream(fr_ctx* ctx, void* s) {
-    return s ? (hipStream_t)s : ctx->own;
-}
+// Asynchronous calls run on the caller's stream; NULL is the null stream.
+hipStream_t pick_stream(fr_ctx*, void* s) { return (hipStream_t)s; }
+
+// fr_solve captures a graph, which the null stream cannot do: a NULL stream
+// is replaced by the context's own stream, ordered after the null stream's
+// prior work (the call synchronises its own stream before returning).
+hipStream_t capture_stream(fr_ctx* ctx, void* s) { return s ? (hipStream_t)s : ctx->own; }
 
 FwdArgs fwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     FwdArgs a{};
@@ -502,7 +506,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     Shape sh;
     if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, K, &sh))) return st;
     FR_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = pick_stream(ctx, stream);
+    hipStream_t s = capture_stream(ctx, stream);
     if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
     char* w = (char*)ws;
     WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
@@ -639,7 +643,7 @@ fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* op
     const PlainLayout Lw = plain_layout(prob);
     if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
     FR_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = pick_stream(ctx, stream);
+    hipStream_t s = capture_stream(ctx, stream);
     if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
     char* w = (char*)ws;
     PlainBufs b;

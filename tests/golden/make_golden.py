@@ -11,8 +11,13 @@ the GPU library.
                      (eps 0.02, T 200, N 100, Adam lr 0.1 eps) run by the
                      FP64 oracle: F_0..F_N and the final impacts.  Takes a
                      few minutes on 8 cores.
+  c3_grad.npz        the 10000 x 300 x 20 gradient workload (eps 0.02, T 300)
+                     at C = 0 and at C ~ N(0, (2 eps)^2): the oracle's
+                     impacts and F, its reverse-mode dF/dC and dF/dr for 8
+                     sampled consumers, and FP64 central differences
+                     (h = 1e-4) at 64 cost and 64 relevance coordinates.
 
-Usage:  python tests/golden/make_golden.py [tiny] [c2]
+Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3]
 """
 import json
 import os
@@ -81,9 +86,68 @@ def c2():
     print("c2", dt, res["F_hist"][0], res["F_hist"][-1])
 
 
+def _consumer_y(r_u, e, C_u, eps, T):
+    """y_i = r_ui sum_{k<m} e_k x_uik for one consumer (oracle forward)."""
+    X = oracle.forward(C_u[None], eps, T)[0]
+    m = X.shape[1]
+    return r_u * (X[:, : m - 1] @ e)
+
+
+def c3():
+    inst = W.config("C3")
+    U, I, m, T = inst.U, inst.I, inst.m, inst.T
+    eps = float(inst.eps)
+    r = inst.r.astype(np.float64)
+    e = inst.e.astype(np.float64)
+    rng = np.random.default_rng(34)
+    users = np.sort(rng.choice(U, size=8, replace=False))
+    cu = users[rng.integers(0, 8, 64)]
+    ci = rng.integers(0, I, 64)
+    ck = rng.integers(0, m, 64)
+    ru = users[rng.integers(0, 8, 64)]
+    ri = rng.integers(0, I, 64)
+    h = 1e-4
+    out = {"users": users, "c_u": cu, "c_i": ci, "c_k": ck, "r_u": ru, "r_i": ri, "h": h}
+    for tag, C in (("zero", np.zeros((U, I, m), dtype=np.float32)),
+                   ("rand", W.random_costs(U, I, m, 2 * eps, seed=33))):
+        t0 = time.time()
+        X = oracle.forward(C, eps, T)
+        imp = oracle.impact(r, e, X)
+        del X
+        F = oracle.nsw(imp)
+        gC, gr = oracle.grad(r[users], e, eps, T, C[users], imp=imp)
+        fdC = np.empty(64)
+        for j in range(64):
+            u, i, k = int(cu[j]), int(ci[j]), int(ck[j])
+            base = _consumer_y(r[u], e, C[u].astype(np.float64), eps, T)
+            Cp = C[u].astype(np.float64)
+            Cp[i, k] += h
+            Cm = C[u].astype(np.float64)
+            Cm[i, k] -= h
+            dp = _consumer_y(r[u], e, Cp, eps, T) - base
+            dm = _consumer_y(r[u], e, Cm, eps, T) - base
+            fdC[j] = (np.sum(np.log1p(dp / imp)) - np.sum(np.log1p(dm / imp))) / (2 * h)
+        fdr = np.empty(64)
+        for j in range(64):
+            u, i = int(ru[j]), int(ri[j])
+            Xu = oracle.forward(C[u][None].astype(np.float64), eps, T)[0]
+            s = float(Xu[i, : m - 1] @ e)
+            fdr[j] = (np.log1p(h * s / imp[i]) - np.log1p(-h * s / imp[i])) / (2 * h)
+        out[f"{tag}_imp"] = imp
+        out[f"{tag}_F"] = np.array([F])
+        out[f"{tag}_dC"] = gC.astype(np.float32)
+        out[f"{tag}_dr"] = gr.astype(np.float32)
+        out[f"{tag}_fdC"] = fdC
+        out[f"{tag}_fdr"] = fdr
+        print("c3", tag, time.time() - t0, F)
+    np.savez_compressed(os.path.join(HERE, "c3_grad.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["tiny"]
     if "tiny" in which:
         tiny()
     if "c2" in which:
         c2()
+    if "c3" in which:
+        c3()
