@@ -157,6 +157,24 @@ fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* op
                          void* stream);
 fr_status fr_workspace_bytes_plain(const fr_problem* prob, size_t* out);
 
+/* Many independent instances of uneven (U, I, m) solved together: every phase
+ * of an outer step (forward, impact/F reduction, backward + update) is one
+ * persistent kernel per column class whose blocks take (instance, consumer
+ * block) work items, longest first, from a device counter until the list is
+ * exhausted; the outer step is captured as one HIP graph and replayed N
+ * times.  probs (host array of n_inst fr_problem, device r and e), and host
+ * arrays of device pointers: C [n_inst] (each [U][I][m], in/out), adam_m,
+ * adam_v [n_inst] (NULL or entries ignored for FR_GD), X [n_inst] (NULL or
+ * NULL entries: not written) and F_hist [n_inst] (each N+1 doubles).  Each
+ * instance's results equal those of fr_solve on it.  Synchronises. */
+fr_status fr_workspace_bytes_batched(int32_t n_inst, const fr_problem* probs,
+                                     const fr_optim* optim, size_t* out);
+fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
+                           const fr_optim* optim, float* const* C, float* const* adam_m,
+                           float* const* adam_v, int64_t start_step, void* const* X,
+                           fr_dtype x_dtype, double* const* F_hist, void* ws, size_t ws_bytes,
+                           void* stream);
+
 /* ------------------------------------------------------------ utilities */
 /* Synchronises the stream and returns the device flags recorded in ws
  * (FR_E_NONFINITE / FR_E_ZERO_IMPACT), then clears them. */

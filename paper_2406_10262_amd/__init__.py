@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "load", "library_path", "FairRankError", "Context", "Problem", "step", "nsw",
-    "backward", "solve", "solve_plain", "SinkhornNSW", "sinkhorn_nsw",
+    "backward", "solve", "solve_plain", "solve_batched", "SinkhornNSW", "sinkhorn_nsw",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,11 +85,14 @@ def load():
     lib.fr_solve.argtypes = [P, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_solve_plain.argtypes = [P, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_sync_status.argtypes = [P, P, P]
+    lib.fr_workspace_bytes_batched.argtypes = [I32, PP, PO, ctypes.POINTER(SZ)]
+    lib.fr_solve_batched.argtypes = [P, I32, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_get_launch.argtypes = [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
+                 "fr_workspace_bytes_batched", "fr_solve_batched",
                  "fr_set_launch", "fr_get_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -306,6 +309,46 @@ def solve_plain(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "ada
     """fr_solve_plain: the unfused baseline form (one launch per half-iteration)."""
     return _solve(load().fr_solve_plain, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom,
                   vel, start_step, 1, want_X, x_dtype, True)
+
+
+def solve_batched(ctx: Context, probs, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,
+                  beta2: float = 0.999, adam_eps: float = 1e-8, C0=None, K: int = 1,
+                  want_X: bool = True, x_dtype: str = "f32"):
+    """fr_solve_batched: Algorithm 1 on many instances at once (persistent
+    kernels, one graph per outer step).  Returns a list of dicts like solve()."""
+    n = len(probs)
+    dev = ctx.device
+    Cs, Ms, Vs, Xs, Fs = [], [], [], [], []
+    for j, p in enumerate(probs):
+        C = torch.zeros((p.U, p.I, p.m), dtype=torch.float32, device=dev) if C0 is None \
+            else C0[j].clone()
+        _f32(C, (p.U, p.I, p.m), "C")
+        Cs.append(C)
+        if rule == "adam":
+            Ms.append(torch.zeros_like(C))
+            Vs.append(torch.zeros_like(C))
+        Xs.append(torch.empty((p.U, p.I, p.m), dtype=torch.bfloat16 if x_dtype == "bf16"
+                              else torch.float32, device=dev) if want_X else None)
+        Fs.append(torch.empty(N + 1, dtype=torch.float64, device=dev))
+    PArr = _Problem * n
+    parr = PArr(*[p.c() for p in probs])
+    VP = ctypes.c_void_p * n
+    cptr = VP(*[t.data_ptr() for t in Cs])
+    mptr = VP(*[t.data_ptr() for t in Ms]) if rule == "adam" else None
+    vptr = VP(*[t.data_ptr() for t in Vs]) if rule == "adam" else None
+    xptr = VP(*[(t.data_ptr() if t is not None else None) for t in Xs]) if want_X else None
+    fptr = VP(*[t.data_ptr() for t in Fs])
+    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K)
+    nb = ctypes.c_size_t()
+    lib = load()
+    _check(lib.fr_workspace_bytes_batched(n, parr, ctypes.byref(o), ctypes.byref(nb)),
+           "fr_workspace_bytes_batched")
+    ws = ctx.workspace(nb.value)
+    _check(lib.fr_solve_batched(ctx.handle, n, parr, ctypes.byref(o), cptr, mptr, vptr, 0, xptr,
+                                FR_BF16 if x_dtype == "bf16" else FR_F32, fptr, _ptr(ws),
+                                ws.numel(), _stream(dev)), "fr_solve_batched")
+    return [{"C": Cs[j], "X": Xs[j], "F_hist": Fs[j], "mom": Ms[j] if Ms else None,
+             "vel": Vs[j] if Vs else None} for j in range(n)]
 
 
 # --------------------------------------------------------------------------

@@ -325,6 +325,177 @@ fr_status read_flags(WsHeader* h, hipStream_t s, bool clear) {
     return FR_OK;
 }
 
+// ---------------------------------------------------------------- batched
+// Launch shape of one instance inside the persistent kernels: blocks of 256
+// threads, teams of L <= 256 lanes, LDS within 64 KB.
+struct BatchShape {
+    const FusedEntry* fe;
+    int L, R, mp, teams;
+    size_t lds_fwd, lds_bwd;
+};
+
+fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
+    const Registry& reg = registry();
+    const int mp = reg.mp_for(m);
+    if (mp < 0) return FR_E_UNSUPPORTED;
+    const int BL = (K <= 1) ? kLoadBlock : K;
+    auto fits = [&](int L, int R, const FusedEntry** fe_out, size_t* lf, size_t* lb) {
+        if (!lanes_ok(L) || L > 256 || (int64_t)L * R < I) return false;
+        const FusedEntry* fe = reg.find(mp, R, 256);
+        if (!fe) return false;
+        const int W = (L + 63) / 64;
+        const int teams = 256 / L;
+        const size_t per_b = (size_t)((BL + 1) * mp + 2 * W * mp) * sizeof(float);
+        if (teams * per_b > kMaxLds) return false;
+        *fe_out = fe;
+        *lf = (size_t)teams * 2 * W * mp * sizeof(float);
+        *lb = teams * per_b;
+        return true;
+    };
+    auto it = ctx->launch.find({I, m});
+    if (it != ctx->launch.end()) {
+        const FusedEntry* fe;
+        size_t lf, lb;
+        if (fits(it->second.first, it->second.second, &fe, &lf, &lb)) {
+            *bs = BatchShape{fe, it->second.first, it->second.second, mp, 256 / it->second.first, lf, lb};
+            return FR_OK;
+        }
+    }
+    double best = 1e300;
+    bool found = false;
+    const int Ls[] = {8, 16, 32, 64, 128, 256};
+    for (int L : Ls) {
+        for (auto& e : reg.all) {
+            if (e.mp != mp || e.lb != 256) continue;
+            const int R = e.rows;
+            if ((int64_t)L * (R - 1) >= I) continue;
+            const FusedEntry* fe;
+            size_t lf, lb;
+            if (!fits(L, R, &fe, &lf, &lb)) continue;
+            const double c = model_cost(I, mp, L, R) * (R * mp > 64 ? 1.5 : 1.0);
+            if (c < best) {
+                best = c;
+                *bs = BatchShape{fe, L, R, mp, 256 / L, lf, lb};
+                found = true;
+            }
+        }
+    }
+    return found ? FR_OK : FR_E_UNSUPPORTED;
+}
+
+struct BatchInst {
+    BatchShape sh;
+    size_t imp, partial, y, hist;   // workspace offsets
+    int nchunk, nck;
+};
+
+struct BatchPlan {
+    std::vector<BatchInst> inst;
+    std::vector<const FusedEntry*> classes;           // distinct kernels
+    std::vector<std::vector<BatchItem>> items;        // per class, longest first
+    std::vector<size_t> lds_fwd, lds_bwd;             // per class
+    std::vector<int2> tab1, tab2;                     // reduction tables
+    size_t hdr, counters, d_fwd, d_fin, d_bwd, d_red, d_items, d_tab1, d_tab2, total;
+    size_t n_items_total;
+};
+
+fr_status plan_batch(fr_ctx* ctx, int n, const fr_problem* probs, int K, BatchPlan* P) {
+    P->inst.resize(n);
+    size_t off = 0;
+    P->hdr = off;
+    off += align_up(sizeof(WsHeader));
+    for (int j = 0; j < n; ++j) {
+        const fr_problem& p = probs[j];
+        BatchInst& b = P->inst[j];
+        fr_status st = batch_shape(ctx, p.n_items, p.m, K, &b.sh);
+        if (st) return st;
+        b.nchunk = impact_chunks(p.n_users, p.n_items);
+        b.nck = n_checkpoints(p.sinkhorn_iters, K);
+        b.imp = off;
+        off += align_up(sizeof(double) * p.n_items);
+        b.partial = off;
+        off += align_up(sizeof(double) * (size_t)b.nchunk * p.n_items);
+        b.y = off;
+        off += align_up(sizeof(float) * (size_t)p.n_users * p.n_items);
+        b.hist = off;
+        off += align_up(sizeof(float) * (size_t)p.n_users * b.nck * p.m);
+    }
+    // classes and items
+    P->classes.clear();
+    P->items.clear();
+    std::vector<std::vector<std::pair<double, BatchItem>>> tmp;
+    for (int j = 0; j < n; ++j) {
+        const FusedEntry* fe = P->inst[j].sh.fe;
+        size_t c = 0;
+        while (c < P->classes.size() && P->classes[c] != fe) ++c;
+        if (c == P->classes.size()) {
+            P->classes.push_back(fe);
+            tmp.emplace_back();
+            P->lds_fwd.push_back(0);
+            P->lds_bwd.push_back(0);
+        }
+        P->lds_fwd[c] = std::max(P->lds_fwd[c], P->inst[j].sh.lds_fwd);
+        P->lds_bwd[c] = std::max(P->lds_bwd[c], P->inst[j].sh.lds_bwd);
+        const int teams = P->inst[j].sh.teams;
+        const double cost = (double)teams * probs[j].n_items * probs[j].m * probs[j].sinkhorn_iters;
+        for (int64_t u0 = 0; u0 < probs[j].n_users; u0 += teams) {
+            BatchItem it;
+            it.inst = j;
+            it.pad = 0;
+            it.u0 = u0;
+            tmp[c].push_back({cost, it});
+        }
+    }
+    P->n_items_total = 0;
+    for (auto& v : tmp) {
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<double, BatchItem>& a,
+                                                const std::pair<double, BatchItem>& b) {
+            return a.first > b.first;
+        });
+        std::vector<BatchItem> its;
+        its.reserve(v.size());
+        for (auto& x : v) its.push_back(x.second);
+        P->n_items_total += its.size();
+        P->items.push_back(std::move(its));
+    }
+    // reduction tables
+    P->tab1.clear();
+    P->tab2.clear();
+    for (int j = 0; j < n; ++j) {
+        for (int c = 0; c < P->inst[j].nchunk; ++c) P->tab1.push_back(make_int2(j, c));
+        for (int g = 0; g < impact_item_groups(probs[j].n_items); ++g) P->tab2.push_back(make_int2(j, g));
+    }
+    // table sizes are bounded independently of the launch choices, so that
+    // fr_workspace_bytes_batched does not depend on a context's overrides
+    int64_t users = 0;
+    for (int j = 0; j < n; ++j) users += probs[j].n_users;
+    P->counters = off;
+    off += align_up(sizeof(unsigned) * n);
+    P->d_fwd = off;
+    off += align_up(sizeof(FwdArgs) * n);
+    P->d_fin = off;
+    off += align_up(sizeof(FwdArgs) * n);
+    P->d_bwd = off;
+    off += align_up(sizeof(BwdArgs) * n);
+    P->d_red = off;
+    off += align_up(sizeof(RedDesc) * n);
+    P->d_items = off;
+    off += align_up(sizeof(BatchItem) * (size_t)users);
+    P->d_tab1 = off;
+    off += align_up(sizeof(int2) * P->tab1.size());
+    P->d_tab2 = off;
+    off += align_up(sizeof(int2) * P->tab2.size());
+    P->total = off;
+    return FR_OK;
+}
+
+__global__ void k_batch_phase(WsHeader* h, unsigned* counters, int n, int advance) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int q = 0; q < n; ++q) counters[q] = 0u;
+        if (advance) h->step = h->step + 1;
+    }
+}
+
 }  // namespace
 
 // ======================================================================== ABI
@@ -674,6 +845,169 @@ fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* op
     launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr, 0, s);
     FR_TRY(hipGetLastError());
     return read_flags(b.hdr, s, false);
+}
+
+fr_status fr_workspace_bytes_batched(int32_t n_inst, const fr_problem* probs,
+                                     const fr_optim* optim, size_t* out) {
+    if (!out || !probs) return FR_E_NULL;
+    if (n_inst < 1) return FR_E_SHAPE;
+    for (int j = 0; j < n_inst; ++j) {
+        fr_status st = check_problem(&probs[j]);
+        if (st) return st;
+    }
+    fr_ctx tmp;   // default launch choices
+    BatchPlan P;
+    fr_status st = plan_batch(&tmp, n_inst, probs, optim ? resolve_k(optim->checkpoint_every) : 1, &P);
+    if (st) return st;
+    *out = P.total;
+    return FR_OK;
+}
+
+fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
+                           const fr_optim* optim, float* const* C, float* const* adam_m,
+                           float* const* adam_v, int64_t start_step, void* const* X,
+                           fr_dtype x_dtype, double* const* F_hist, void* ws, size_t ws_bytes,
+                           void* stream) {
+    if (!ctx || !optim || !probs || !C || !F_hist || !ws) return FR_E_NULL;
+    if (n_inst < 1) return FR_E_SHAPE;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    for (int j = 0; j < n_inst; ++j) {
+        fr_status st = check_problem(&probs[j]);
+        if (st) return st;
+        if (!C[j] || !F_hist[j]) return FR_E_NULL;
+        st = check_optim(optim, adam_m ? adam_m[j] : nullptr, adam_v ? adam_v[j] : nullptr,
+                         start_step);
+        if (st) return st;
+    }
+    const int K = resolve_k(optim->checkpoint_every);
+    BatchPlan P;
+    fr_status st = plan_batch(ctx, n_inst, probs, K, &P);
+    if (st) return st;
+    if (ws_bytes < P.total) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = capture_stream(ctx, stream);
+    if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
+    char* w = (char*)ws;
+    WsHeader* hdr = (WsHeader*)(w + P.hdr);
+    unsigned* counters = (unsigned*)(w + P.counters);
+
+    // descriptors
+    std::vector<FwdArgs> fa(n_inst), ff(n_inst);
+    std::vector<BwdArgs> ba(n_inst);
+    std::vector<RedDesc> rd(n_inst);
+    for (int j = 0; j < n_inst; ++j) {
+        const fr_problem* p = &probs[j];
+        const BatchInst& b = P.inst[j];
+        Shape sh{};
+        sh.L = b.sh.L;
+        FwdArgs a = fwd_args(p, sh, C[j]);
+        a.y = (float*)(w + b.y);
+        a.hist = (float*)(w + b.hist);
+        a.K = K;
+        a.nck = b.nck;
+        fa[j] = a;
+        a.hist = nullptr;
+        a.X = X ? X[j] : nullptr;
+        a.x_bf16 = (x_dtype == FR_BF16);
+        ff[j] = a;
+        BwdArgs g = bwd_args(p, sh, C[j]);
+        g.hist = (float*)(w + b.hist);
+        g.K = K;
+        g.nck = b.nck;
+        g.imp = (double*)(w + b.imp);
+        g.Cw = C[j];
+        g.mom = adam_m ? adam_m[j] : nullptr;
+        g.vel = adam_v ? adam_v[j] : nullptr;
+        g.step_ptr = &hdr->step;
+        g.rule = optim->rule;
+        g.lr = optim->lr;
+        g.b1 = optim->beta1;
+        g.b2 = optim->beta2;
+        g.aeps = optim->adam_eps;
+        ba[j] = g;
+        RedDesc r;
+        r.y = (const float*)(w + b.y);
+        r.partial = (double*)(w + b.partial);
+        r.imp = (double*)(w + b.imp);
+        r.F_hist = F_hist[j];
+        r.U = p->n_users;
+        r.I = p->n_items;
+        r.nchunk = b.nchunk;
+        rd[j] = r;
+    }
+    std::vector<BatchItem> all_items;
+    std::vector<size_t> item_off;
+    for (auto& v : P.items) {
+        item_off.push_back(all_items.size());
+        all_items.insert(all_items.end(), v.begin(), v.end());
+    }
+    FR_TRY(hipMemcpyAsync(w + P.d_fwd, fa.data(), sizeof(FwdArgs) * n_inst, hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_fin, ff.data(), sizeof(FwdArgs) * n_inst, hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_bwd, ba.data(), sizeof(BwdArgs) * n_inst, hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_red, rd.data(), sizeof(RedDesc) * n_inst, hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_items, all_items.data(), sizeof(BatchItem) * all_items.size(),
+                          hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_tab1, P.tab1.data(), sizeof(int2) * P.tab1.size(),
+                          hipMemcpyHostToDevice, s));
+    FR_TRY(hipMemcpyAsync(w + P.d_tab2, P.tab2.data(), sizeof(int2) * P.tab2.size(),
+                          hipMemcpyHostToDevice, s));
+    FR_TRY(hipStreamSynchronize(s));   // host vectors are released below
+
+    int cus = 0;
+    FR_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int ncls = (int)P.classes.size();
+    const FwdArgs* dfa = (const FwdArgs*)(w + P.d_fwd);
+    const FwdArgs* dff = (const FwdArgs*)(w + P.d_fin);
+    const BwdArgs* dba = (const BwdArgs*)(w + P.d_bwd);
+    const RedDesc* drd = (const RedDesc*)(w + P.d_red);
+    const BatchItem* ditems = (const BatchItem*)(w + P.d_items);
+    const int2* dt1 = (const int2*)(w + P.d_tab1);
+    const int2* dt2 = (const int2*)(w + P.d_tab2);
+    std::vector<int> grid_f(ncls), grid_b(ncls);
+    for (int c = 0; c < ncls; ++c) {
+        const int nit = (int)P.items[c].size();
+        grid_f[c] = std::max(1, std::min(nit, P.classes[c]->occ_bfwd(256, P.lds_fwd[c]) * cus));
+        grid_b[c] = std::max(1, std::min(nit, P.classes[c]->occ_bbwd(256, P.lds_bwd[c]) * cus));
+    }
+    auto forward_phase = [&](const FwdArgs* descs) {
+        hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 0);
+        for (int c = 0; c < ncls; ++c)
+            P.classes[c]->bfwd(descs, ditems + item_off[c], (int)P.items[c].size(), counters + c,
+                               grid_f[c], 256, P.lds_fwd[c], s);
+        launch_impact_batched(drd, n_inst, dt1, (int)P.tab1.size(), dt2, (int)P.tab2.size(),
+                              start_step, hdr, s);
+    };
+    auto backward_phase = [&]() {
+        hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 1);
+        for (int c = 0; c < ncls; ++c)
+            P.classes[c]->bbwd(dba, ditems + item_off[c], (int)P.items[c].size(), counters + c,
+                               grid_b[c], 256, P.lds_bwd[c], s);
+    };
+
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, hdr, start_step);
+    FR_TRY(hipGetLastError());
+    const int N = optim->outer_steps;
+    if (N > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        FR_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        forward_phase(dfa);
+        backward_phase();
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (ce != hipSuccess) return FR_E_DEVICE;
+        ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ce != hipSuccess) {
+            hipGraphDestroy(graph);
+            return FR_E_DEVICE;
+        }
+        for (int q = 0; q < N && ce == hipSuccess; ++q) ce = hipGraphLaunch(exec, s);
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        if (ce != hipSuccess) return FR_E_DEVICE;
+    }
+    forward_phase(dff);
+    FR_TRY(hipGetLastError());
+    return read_flags(hdr, s, false);
 }
 
 }  // extern "C"

@@ -164,12 +164,12 @@ __device__ __forceinline__ void load_costs(const float* C, int64_t u, bool activ
 }
 
 // ---------------------------------------------------------------------------
-template <int MP, int R, int LB>
-__global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
-    extern __shared__ float smem[];
+// Forward for the teams of one block: team q of the block owns consumer
+// u_first + q.
+template <int MP, int R>
+__device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
-    const int teams = blockDim.x / a.L;
-    const int64_t u = (int64_t)blockIdx.x * teams + tm.team;
+    const int64_t u = u_first + tm.team;
     const bool active = u < a.U;
     const int I = a.I, m = a.m;
     float* red = smem + tm.team * (2 * tm.W * MP);
@@ -238,13 +238,18 @@ __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
 template <int MP, int R, int LB>
-__global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
+__global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
     extern __shared__ float smem[];
+    fwd_body<MP, R>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+}
+
+// ---------------------------------------------------------------------------
+template <int MP, int R>
+__device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int teams = blockDim.x / a.L;
-    const int64_t u = (int64_t)blockIdx.x * teams + tm.team;
+    const int64_t u = u_first + tm.team;
     const bool active = u < a.U;
     const int I = a.I, m = a.m;
     const int BL = (a.K == 1) ? kLoadBlock : a.K;
@@ -424,6 +429,77 @@ __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
 }
 
 template <int MP, int R, int LB>
+__global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
+    extern __shared__ float smem[];
+    bwd_body<MP, R>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernels: every block repeatedly takes the next work item
+// (instance, first consumer) from a global counter and runs the same team
+// body on it, until the list is exhausted.  Items are ordered longest first.
+template <int MP, int R, int LB>
+__global__ __launch_bounds__(LB) void k_bfwd(const FwdArgs* __restrict__ descs,
+                                             const BatchItem* __restrict__ items, int n_items,
+                                             unsigned* counter) {
+    extern __shared__ float smem[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const BatchItem bi = items[it];
+        const FwdArgs a = descs[bi.inst];
+        fwd_body<MP, R>(a, bi.u0, smem);
+    }
+}
+
+template <int MP, int R, int LB>
+__global__ __launch_bounds__(LB) void k_bbwd(const BwdArgs* __restrict__ descs,
+                                             const BatchItem* __restrict__ items, int n_items,
+                                             unsigned* counter) {
+    extern __shared__ float smem[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const BatchItem bi = items[it];
+        const BwdArgs a = descs[bi.inst];
+        bwd_body<MP, R>(a, bi.u0, smem);
+    }
+}
+
+template <int MP, int R, int LB>
+void launch_bfwd(const FwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
+                 size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_bfwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+}
+template <int MP, int R, int LB>
+void launch_bbwd(const BwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
+                 size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_bbwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+}
+template <int MP, int R, int LB>
+int occupancy_bfwd(int block, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, LB>, block, lds) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+template <int MP, int R, int LB>
+int occupancy_bbwd(int block, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, LB>, block, lds) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <int MP, int R, int LB>
 void launch_fwd(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_fwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, a);
 }
@@ -434,7 +510,15 @@ void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s
 
 template <int R, int LB>
 constexpr FusedEntry entry() {
-    return FusedEntry{FR_MP, R, LB, &launch_fwd<FR_MP, R, LB>, &launch_bwd<FR_MP, R, LB>};
+    return FusedEntry{FR_MP,
+                      R,
+                      LB,
+                      &launch_fwd<FR_MP, R, LB>,
+                      &launch_bwd<FR_MP, R, LB>,
+                      &launch_bfwd<FR_MP, R, LB>,
+                      &launch_bbwd<FR_MP, R, LB>,
+                      &occupancy_bfwd<FR_MP, R, LB>,
+                      &occupancy_bbwd<FR_MP, R, LB>};
 }
 
 // Rows per lane instantiated for this column class: the register-resident

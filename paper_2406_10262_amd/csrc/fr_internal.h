@@ -54,13 +54,29 @@ struct BwdArgs {
     float c2, inv_eps, lr, b1, b2, aeps;
 };
 
+// One work item of the batched kernels: a block of consumers of one instance.
+struct BatchItem {
+    int inst;
+    int pad;
+    int64_t u0;   // first consumer of the block
+};
+
 typedef void (*FwdLaunch)(const FwdArgs&, int grid, int block, size_t lds, hipStream_t);
 typedef void (*BwdLaunch)(const BwdArgs&, int grid, int block, size_t lds, hipStream_t);
+typedef void (*BFwdLaunch)(const FwdArgs*, const BatchItem*, int n, unsigned* counter, int grid,
+                           int block, size_t lds, hipStream_t);
+typedef void (*BBwdLaunch)(const BwdArgs*, const BatchItem*, int n, unsigned* counter, int grid,
+                           int block, size_t lds, hipStream_t);
+typedef int (*Occupancy)(int block, size_t lds);
 
 struct FusedEntry {
     int mp, rows, lb;   // padded columns, rows per lane, launch bound (max block)
     FwdLaunch fwd;
     BwdLaunch bwd;
+    BFwdLaunch bfwd;    // persistent batched forms
+    BBwdLaunch bbwd;
+    Occupancy occ_bfwd;
+    Occupancy occ_bbwd;
 };
 
 // Instantiated column classes.  Each class is compiled in its own translation
@@ -80,6 +96,20 @@ void launch_impact(const float* y, int64_t U, int I, double* partial, int nchunk
 void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const float* e, int64_t U,
                            int I, int m, float* y, hipStream_t s);
 int impact_chunks(int64_t U, int I);
+
+// Batched impact reduction: one descriptor per instance.
+struct RedDesc {
+    const float* y;     // [U][I]
+    double* partial;    // [nchunk][I]
+    double* imp;        // [I]
+    double* F_hist;     // F history of the instance (device)
+    int64_t U;
+    int I, nchunk;
+};
+void launch_impact_batched(const RedDesc* descs, int n_inst, const int2* tab1, int n1,
+                           const int2* tab2, int n2, int64_t start_step, WsHeader* hdr,
+                           hipStream_t s);
+int impact_item_groups(int I);
 
 // Unfused baseline form (fr_plain.hip).
 struct PlainBufs {

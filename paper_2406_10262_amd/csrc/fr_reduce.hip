@@ -104,7 +104,77 @@ __global__ __launch_bounds__(256) void k_rows_from_plan(const void* X, int bf16,
     y[row] = r[row] * s;
 }
 
+// ---- batched forms: blockIdx.x indexes a host-built table of (instance, part)
+__global__ __launch_bounds__(256) void k_bimp_partial(const RedDesc* __restrict__ descs,
+                                                      const int2* __restrict__ tab) {
+    const int2 t = tab[blockIdx.x];
+    const RedDesc d = descs[t.x];
+    const int64_t u0 = (int64_t)t.y * kChunk;
+    for (int i = threadIdx.x; i < d.I; i += blockDim.x) {
+        float v[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) v[q] = (u0 + q < d.U) ? d.y[(u0 + q) * d.I + i] : 0.f;
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) sacc += (double)v[q];
+        d.partial[(int64_t)t.y * d.I + i] = sacc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bimp_items(const RedDesc* __restrict__ descs,
+                                                    const int2* __restrict__ tab) {
+    __shared__ double red[256];
+    const int2 t = tab[blockIdx.x];
+    const RedDesc d = descs[t.x];
+    const int lane = threadIdx.x % kItemLanes;
+    const int i = t.y * (256 / kItemLanes) + threadIdx.x / kItemLanes;
+    double sacc = 0.0;
+    if (i < d.I)
+        for (int c = lane; c < d.nchunk; c += kItemLanes) sacc += d.partial[(int64_t)c * d.I + i];
+    red[threadIdx.x] = sacc;
+    __syncthreads();
+    for (int w = kItemLanes / 2; w > 0; w >>= 1) {
+        if (lane < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (i < d.I && lane == 0) d.imp[i] = red[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_bimp_final(const RedDesc* __restrict__ descs,
+                                                    int64_t start_step, WsHeader* hdr) {
+    __shared__ double red[256];
+    const RedDesc d = descs[blockIdx.x];
+    double lsum = 0.0;
+    uint32_t fl = 0;
+    for (int i = threadIdx.x; i < d.I; i += blockDim.x) {
+        const double v = d.imp[i];
+        if (!isfinite(v))
+            fl |= FLAG_NONFINITE;
+        else if (!(v > 0.0))
+            fl |= FLAG_ZERO_IMPACT;
+        lsum += log(v);
+    }
+    if (fl) atomicOr(&hdr->flags, fl);
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && d.F_hist) d.F_hist[hdr->step - start_step] = red[0];
+}
+
 }  // namespace
+
+void launch_impact_batched(const RedDesc* descs, int n_inst, const int2* tab1, int n1,
+                           const int2* tab2, int n2, int64_t start_step, WsHeader* hdr,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_bimp_partial, dim3(n1), dim3(256), 0, s, descs, tab1);
+    hipLaunchKernelGGL(k_bimp_items, dim3(n2), dim3(256), 0, s, descs, tab2);
+    hipLaunchKernelGGL(k_bimp_final, dim3(n_inst), dim3(256), 0, s, descs, start_step, hdr);
+}
+
+int impact_item_groups(int I) { return (I + 256 / kItemLanes - 1) / (256 / kItemLanes); }
 
 int impact_chunks(int64_t U, int I) {
     (void)I;

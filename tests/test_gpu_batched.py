@@ -1,0 +1,87 @@
+"""Batched solver (fr_solve_batched): uneven instances in persistent kernels.
+Each instance must equal the single-instance solver run with the same launch
+shape, and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import F_REL, device_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances():
+    # the batched workload's generator at smaller U, plus ragged extremes
+    shapes = W.batched_shapes(128, seed=4)[:12]
+    out = [W.batched_instance(j, (min(U, 150), I, m), T=40, N=6)
+           for j, (U, I, m) in enumerate(shapes)]
+    out.append(W.small_instance(3, 7, 7, seed=91, eps=0.03, T=40, N=6))
+    out.append(W.small_instance(1, 2, 2, seed=92, eps=0.03, T=40, N=6))
+    return out
+
+
+def _pin_launch(ctx, insts):
+    """Same team shape for the batched and the single-instance kernels."""
+    for x in insts:
+        ctx.set_launch(x.I, x.m, 256, 1 if x.I <= 256 else 2)
+
+
+@pytest.fixture(scope="module")
+def adam_run(fr):
+    insts = _instances()
+    ctx = fr.Context(0)
+    _pin_launch(ctx, insts)
+    probs = [device_problem(fr, x.r, x.e, x.eps, x.T) for x in insts]
+    print("case batched Adam solve of", len(insts), "instances", flush=True)
+    res = fr.solve_batched(ctx, probs, 6, 0.003)
+    torch.cuda.synchronize()
+    return insts, probs, res, ctx
+
+
+def test_batched_equals_single_instance_solver(fr, adam_run):
+    insts, probs, res, ctx = adam_run
+    for j, (x, p) in enumerate(zip(insts, probs)):
+        print(f"case instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
+        one = fr.solve(ctx, p, 6, 0.003)
+        assert torch.equal(res[j]["C"], one["C"])
+        assert torch.equal(res[j]["X"], one["X"])
+        assert torch.equal(res[j]["mom"], one["mom"]) and torch.equal(res[j]["vel"], one["vel"])
+        Fb = res[j]["F_hist"].cpu().numpy()
+        Fs = one["F_hist"].cpu().numpy()
+        assert np.max(np.abs(Fb / Fs - 1)) <= 1e-14
+
+
+@pytest.mark.parametrize("j", [0, 3, 7, 12, 13])
+def test_batched_adam_objective_matches_oracle(fr, adam_run, j):
+    """Under Adam the plan itself is ill-conditioned (entries whose exact
+    gradient is ~0 take sign-like steps from rounding noise); the objective
+    and the impacts are not."""
+    insts, probs, res, ctx = adam_run
+    x = insts[j]
+    print(f"case oracle Adam instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
+    ref = oracle.solve(x.r, x.e, float(x.eps), x.T, 6, lr=0.003)
+    Fb = res[j]["F_hist"].cpu().numpy()
+    assert np.max(np.abs(Fb / ref["F_hist"] - 1)) <= F_REL
+    # individual impacts inherit the plan's sign-noise (~1e-4 after a few
+    # steps); F, a sum of their logs, stays within 1e-6.  A gross error in
+    # one item's impact would still show here.
+    imp, _ = fr.nsw(ctx, probs[j], res[j]["X"])
+    assert np.max(np.abs(imp.cpu().numpy() / ref["imp"] - 1)) <= 1e-3
+
+
+@pytest.mark.parametrize("j", [0, 7, 12])
+def test_batched_gradient_ascent_matches_oracle(fr, j):
+    insts = _instances()
+    ctx = fr.Context(0)
+    _pin_launch(ctx, insts)
+    probs = [device_problem(fr, x.r, x.e, x.eps, x.T) for x in insts]
+    res = fr.solve_batched(ctx, probs, 4, 0.5, rule="gd")
+    x = insts[j]
+    print(f"case oracle GD instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
+    ref = oracle.solve(x.r, x.e, float(x.eps), x.T, 4, rule="gd", lr=0.5)
+    assert np.max(np.abs(res[j]["F_hist"].cpu().numpy() / ref["F_hist"] - 1)) <= F_REL
+    assert np.max(np.abs(res[j]["X"].double().cpu().numpy() - ref["X"])) <= 1e-5
+    Cref = ref["C"]
+    assert np.max(np.abs(res[j]["C"].double().cpu().numpy() - Cref)) <= 1e-5 * np.max(np.abs(Cref))
