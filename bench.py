@@ -1,16 +1,23 @@
 """Benchmark of the fused fair-ranking solver on one MI355X.
 
-One bench step = one full solve of Algorithm 1 on the workload: N outer
-steps, each a T-iteration Sinkhorn forward on every consumer's plan, the FP64
-impact and log-NSW reduction, the adjoint backward and the Adam update, plus
-the final forward.  Inputs are resident in HBM before timing starts.
+    python bench.py [--steps K] [--warmup W] [--workload C2|C1|C3|C4|C5]
 
-    python bench.py [--steps K] [--warmup W] [--workload C2]
+One bench step is one pass of the whole hot path over the workload:
 
-Prints one JSON line with throughput in plan-cells x Sinkhorn-iterations per
-second, the NSW relative error against the FP64 oracle's stored trajectory,
-the plain (unfused) GPU form for comparison, the roofline of the dominant
-kernel (timed with HIP events on its own stream) and the oracle's CPU rate.
+* C1, C2 (default), C5: one full solve of Algorithm 1 -- N outer steps, each
+  a T-iteration Sinkhorn forward on every consumer's plan, the FP64 impact and
+  log-NSW reduction, the adjoint backward and the Adam update -- plus the
+  final forward.  (C5 runs --outer steps, default 2 of its 50, for time.)
+* C3: one gradient evaluation, fr_step then fr_backward with the column
+  potentials kept every 50 iterations.
+* C4: one batched solve of the 128 uneven instances (persistent kernels, one
+  graph per outer step).
+
+Inputs are resident in HBM before timing starts.  Prints one JSON line with
+throughput in plan-cells x Sinkhorn-iterations per second, the NSW relative
+error against the FP64 oracle's stored values, the unfused GPU form for
+comparison, the roofline of the dominant kernel (HIP events on the solve's
+stream) and the oracle's CPU rate on a bounded sample.
 """
 import argparse
 import ctypes
@@ -36,15 +43,9 @@ import numpy as np  # noqa: E402
 # two accumulation FMAs).
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 PEAK_SLOTS = CUS * SIMDS * LANES * CLOCK          # 3.93e13 lane-slots/s
-EXP_PEAK = PEAK_SLOTS / 2                         # v_exp_f32 lanes/s
 FWD_SLOTS = 5
 BWD_SLOTS = 8
-
-
-def workload(name):
-    import workloads as W
-    inst = W.config(name)
-    return inst
+HBM_PEAK = 8.0e12
 
 
 def kernel_source_hash():
@@ -69,12 +70,342 @@ def load_traffic(kernel, cfg):
     return ent.get("bytes_per_launch")
 
 
+def _lib_timing(lib):
+    lib.fr_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.fr_ctx_kernel_times.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+
+
+def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name):
+    """Per-kernel mean launch times with HIP events (one solve in timing
+    mode), and the roofline of the dominant kernel."""
+    import torch
+    _lib_timing(lib)
+    lib.fr_ctx_set_timing(ctx.handle, 1)
+    fr.solve(ctx, prob, N, lr, want_X=False)
+    torch.cuda.synchronize()
+    fms, fn, bms, bn = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    lib.fr_ctx_kernel_times(ctx.handle, ctypes.byref(fms), ctypes.byref(fn), ctypes.byref(bms),
+                            ctypes.byref(bn))
+    lib.fr_ctx_set_timing(ctx.handle, 0)
+    cells = prob.U * prob.I * prob.m
+    per_launch = cells * (prob.T + 1)   # cell-iterations of one launch (incl. plan / init pass)
+    ks = {"k_fwd": (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS),
+          "k_bwd": (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS)}
+    kernels = {k: {"avg_ms": v[0], "launches": v[1],
+                   "cell_iters_per_s": per_launch / (v[0] * 1e-3)} for k, v in ks.items()}
+    dom = max(ks, key=lambda k: ks[k][0])
+    avg_ms, _, slots = ks[dom]
+    achieved = per_launch * slots / (avg_ms * 1e-3)
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
+            "peak": PEAK_SLOTS / 1e12, "unit": "T VALU lane-slots/s",
+            "frac": achieved / PEAK_SLOTS, "traffic": load_traffic(dom, cfg_name),
+            "avg_launch_ms": avg_ms,
+            "model": f"{slots} non-transcendental VALU lane-slots per cell-iteration (the "
+                     "exponential overlaps on its own half-rate pipe), U*I*m*(T+1) "
+                     "cell-iterations per launch; peak = 256 CUs x 64 lanes x 2.4 GHz"}
+    print(f"bench: kernels fwd {ks['k_fwd'][0]:.3f} ms bwd {ks['k_bwd'][0]:.3f} ms per launch",
+          flush=True)
+    return kernels, roof
+
+
+def measured_peaks(lib):
+    lib.fr_diag_alu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    diag = {}
+    for kind, name in ((0, "exp2_per_s"), (1, "fma_per_s"), (2, "exp_plus_5fma_per_s")):
+        ms, ops = ctypes.c_double(), ctypes.c_double()
+        if lib.fr_diag_alu(kind, 256 * 32, 2000, ctypes.byref(ms), ctypes.byref(ops)) == 0:
+            diag[name] = ops.value / (ms.value * 1e-3)
+    return diag
+
+
+def base_record(args, value, ms_per_step, config):
+    return {"metric": "plan-cells·Sinkhorn-iters/s", "value": value, "unit": "cell-iters/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
+
+
+# ---------------------------------------------------------------------------
+def bench_solve(args, fr, lib, dev, name):
+    """C1, C2, C5: full solves of one instance."""
+    import torch
+    import workloads as W
+    inst = W.config(name)
+    U, I, m, T = inst.U, inst.I, inst.m, inst.T
+    N = inst.N if name != "C5" else args.outer
+    x_dtype = "bf16" if name == "C5" else "f32"
+    cells = U * I * m
+    work = cells * T * N
+    ctx = fr.Context(0)
+    prob = fr.Problem(torch.from_numpy(inst.r).to(dev), torch.from_numpy(inst.e).to(dev),
+                      float(inst.eps), T)
+    lr = float(inst.lr)
+    if args.autotune:
+        ctx.autotune(prob)
+    print(f"bench: workload {inst.name} U={U} I={I} m={m} T={T} N={N} "
+          f"launch={ctx.get_launch(I, m)}", flush=True)
+    for _ in range(args.warmup):
+        res = fr.solve(ctx, prob, N, lr, x_dtype=x_dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = fr.solve(ctx, prob, N, lr, x_dtype=x_dtype)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = work * args.steps / dt
+    print(f"bench: fused {ms_per_step:.2f} ms/solve, {value:.4e} cell-iters/s", flush=True)
+    if args.profile:
+        return None
+    Fh = res["F_hist"].cpu().numpy()
+    del res
+    nsw = {"F_0": float(Fh[0]), "F_N": float(Fh[-1])}
+    ref = None
+    gold = os.path.join(ROOT, "tests", "golden", f"{inst.name.lower()}_trajectory.json")
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            ref = np.array(json.load(fh)["F_hist"])
+        nsw["rel_err_max"] = float(np.max(np.abs(Fh / ref - 1)))
+        nsw["rel_err_final"] = float(abs(Fh[-1] / ref[-1] - 1))
+        nsw["reference"] = "FP64 oracle trajectory (tests/golden)"
+    if name == "C5":
+        nsw.update(c5_subsample_error(fr, dev, inst))
+    kernels, roof = kernel_roofline(fr, lib, ctx, prob, min(N, 20), lr, inst.name)
+    desc = {"C1": "low-dimensional uniform-relevance", "C2": "low-rank-16 sigmoid relevance",
+            "C5": "low-rank-32 sigmoid relevance, plans stored in BF16"}[name]
+    config = {"workload": f"{inst.name}: U={U} consumers, I={I} items, m={m} positions "
+                          f"(incl. dummy), {desc}, e_k=1/log2(k+1), eps={float(inst.eps):.4g}, "
+                          f"T={T} Sinkhorn iterations, N={N} Adam steps (lr=0.1 eps), FP32 "
+                          f"log-domain Sinkhorn, FP64 impacts and log-NSW",
+              "step": "one full solve (N outer steps + final forward)",
+              "cells": cells, "cell_iters_per_step": work}
+    out = base_record(args, value, ms_per_step, config)
+    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof})
+    if not args.skip_diag:
+        out["measured_peaks"] = measured_peaks(lib)
+    if not args.skip_plain and name != "C5":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pres = fr.solve_plain(ctx, prob, N, lr, want_X=False)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        pF = pres["F_hist"].cpu().numpy()
+        out["plain_gpu"] = {
+            "value": work / pdt, "ms_per_step": pdt * 1e3,
+            "fused_speedup": (work / (ms_per_step * 1e-3)) / (work / pdt),
+            "F_N": float(pF[-1]), "F_rel_diff_vs_fused": float(np.max(np.abs(pF / Fh - 1))),
+            "form": "one kernel launch per Sinkhorn half-iteration, potentials of every "
+                    "iteration in HBM, reverse sweep reading them back, no graph"}
+        if ref is not None:
+            out["plain_gpu"]["rel_err_max"] = float(np.max(np.abs(pF / ref - 1)))
+        print(f"bench: plain {pdt * 1e3:.1f} ms/solve", flush=True)
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline_solve(inst, name, lr)
+    return out
+
+
+def c5_subsample_error(fr, dev, inst):
+    """NSW error of the 1000-consumer sub-instance against the oracle's
+    stored values (forward at a seeded C, 3 Adam steps from C = 0)."""
+    import torch
+    import workloads as W
+    path = os.path.join(ROOT, "tests", "golden", "c5_sub.npz")
+    if not os.path.exists(path):
+        return {}
+    g = np.load(path)
+    users = g["users"]
+    ctx = fr.Context(0)
+    prob = fr.Problem(torch.from_numpy(inst.r[users]).to(dev), torch.from_numpy(inst.e).to(dev),
+                      float(inst.eps), inst.T)
+    C = torch.from_numpy(W.random_costs(1000, inst.I, inst.m, 2 * float(inst.eps), seed=56)).to(dev)
+    out = fr.step(ctx, prob, C)
+    res = fr.solve(ctx, prob, 3, float(inst.lr), x_dtype="bf16")
+    Fh = res["F_hist"].cpu().numpy()
+    return {"subsample": "1000 consumers (seed 55)",
+            "subsample_forward_F_rel_err": abs(float(out["F"][0]) / float(g["rand_F"][0]) - 1),
+            "subsample_forward_imp_rel_err_max":
+                float(np.max(np.abs(out["imp"].cpu().numpy() / g["rand_imp"] - 1))),
+            "subsample_3step_F_rel_err_max": float(np.max(np.abs(Fh / g["adam_F_hist"] - 1)))}
+
+
+def cpu_baseline_solve(inst, name, lr):
+    import oracle
+    import workloads as W
+    if name == "C5":
+        users = W.subsample_users(inst.U, 20, seed=57)
+        r = inst.r[users]
+        Ns, sample = 1, (f"20 consumers of the C5 instance, 1 outer step (T={inst.T} forward, "
+                         f"gradient, Adam) plus the final forward")
+    else:
+        r = inst.r
+        Ns = 2 if name == "C2" else inst.N
+        sample = (f"full {inst.name} instance, {Ns} of its {inst.N} outer steps (each a "
+                  f"T={inst.T} forward, gradient and Adam update) plus the final forward")
+    cells = r.shape[0] * inst.I * inst.m
+    t0 = time.perf_counter()
+    oracle.solve(r, inst.e, float(inst.eps), inst.T, Ns, lr=lr)
+    cdt = time.perf_counter() - t0
+    print(f"bench: oracle {cdt:.1f} s", flush=True)
+    return {"value": cells * inst.T * Ns / cdt, "unit": "cell-iters/s",
+            "cores": oracle.num_threads(), "kind": "oracle", "seconds": cdt,
+            "sample": sample + "; FP64, OpenMP over consumers"}
+
+
+# ---------------------------------------------------------------------------
+def bench_grad(args, fr, lib, dev):
+    """C3: gradient evaluations (forward + checkpointed adjoint)."""
+    import torch
+    import workloads as W
+    inst = W.config("C3")
+    U, I, m, T = inst.U, inst.I, inst.m, inst.T
+    K = 50
+    cells = U * I * m
+    ctx = fr.Context(0)
+    prob = fr.Problem(torch.from_numpy(inst.r).to(dev), torch.from_numpy(inst.e).to(dev),
+                      float(inst.eps), T)
+    C = torch.from_numpy(W.random_costs(U, I, m, 2 * float(inst.eps), seed=33)).to(dev)
+    if args.autotune:
+        ctx.autotune(prob, C)
+
+    def one():
+        out = fr.step(ctx, prob, C, sync=False)
+        return out, fr.backward(ctx, prob, C, out["imp"], 1.0, want_dr=True, K=K)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, (dC, dr) = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    work = cells * T
+    print(f"bench: C3 gradient {dt * 1e3:.2f} ms", flush=True)
+    rec = {}
+    path = os.path.join(ROOT, "tests", "golden", "c3_grad.npz")
+    if os.path.exists(path):
+        g = np.load(path)
+        users = torch.from_numpy(g["users"].astype(np.int64)).to(dev)
+        ref = g["rand_dC"].astype(np.float64)
+        rec = {"F_rel_err": abs(float(out["F"][0]) / float(g["rand_F"][0]) - 1),
+               "dC_err_rel_to_max": float(np.max(np.abs(dC[users].double().cpu().numpy() - ref))
+                                          / np.max(np.abs(ref))),
+               "reference": "FP64 oracle adjoint, 8 sampled consumers (tests/golden)"}
+    config = {"workload": f"C3: U={U}, I={I}, m={m}, low-rank-16 sigmoid relevance, "
+                          f"eps={float(inst.eps):.4g}, T={T}, gradient dF/dC and dF/dr with "
+                          f"column potentials checkpointed every {K} iterations",
+              "step": "one gradient evaluation (fr_step + fr_backward)",
+              "cells": cells, "cell_iters_per_step": work}
+    out_rec = base_record(args, work / dt, dt * 1e3, config)
+    out_rec["nsw"] = rec
+    if not args.skip_cpu:
+        import oracle
+        users = W.subsample_users(U, 100, seed=35)
+        t0 = time.perf_counter()
+        Cs = C[torch.from_numpy(users).to(dev)].cpu().numpy()
+        X = oracle.forward(Cs, float(inst.eps), T)
+        imp = oracle.impact(inst.r[users], inst.e, X)
+        oracle.grad(inst.r[users], inst.e, float(inst.eps), T, Cs, imp=imp)
+        cdt = time.perf_counter() - t0
+        out_rec["cpu_baseline"] = {"value": 100 * I * m * T / cdt, "unit": "cell-iters/s",
+                                   "cores": oracle.num_threads(), "kind": "oracle",
+                                   "seconds": cdt,
+                                   "sample": "100 consumers: forward, impacts, reverse-mode "
+                                             "gradient (every iterate stored); FP64"}
+    return out_rec
+
+
+# ---------------------------------------------------------------------------
+def bench_batched(args, fr, lib, dev):
+    """C4: the 128 uneven instances solved together."""
+    import torch
+    import workloads as W
+    shapes = W.batched_shapes(128, seed=4)
+    insts = [W.batched_instance(j, s) for j, s in enumerate(shapes)]
+    T, N = insts[0].T, insts[0].N
+    lr = float(insts[0].lr)
+    ctx = fr.Context(0)
+    probs = [fr.Problem(torch.from_numpy(x.r).to(dev), torch.from_numpy(x.e).to(dev),
+                        float(x.eps), T) for x in insts]
+    cells = sum(x.cells for x in insts)
+    work = cells * T * N
+    if args.autotune:
+        seen = set()
+        for p in probs:
+            if (p.I, p.m) not in seen:
+                seen.add((p.I, p.m))
+                ctx.autotune(p, batched=True)
+    print(f"bench: workload C4 128 instances, {cells:.3e} cells, T={T}, N={N}", flush=True)
+    for _ in range(args.warmup):
+        res = fr.solve_batched(ctx, probs, N, lr, want_X=False)
+        del res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = fr.solve_batched(ctx, probs, N, lr, want_X=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(f"bench: batched {dt:.2f} s/solve, {work / dt:.4e} cell-iters/s", flush=True)
+    Fb = [r["F_hist"].cpu().numpy() for r in res]
+    del res
+    config = {"workload": "C4: 128 instances, U~U[100,5000], I~U[20,500], m~U[5,50] (m<=I), "
+                          "low-rank-16 sigmoid relevance, eps=0.03, T=200, N=50 Adam steps, FP32",
+              "step": "one batched solve of all 128 instances",
+              "cells": cells, "cell_iters_per_step": work}
+    out = base_record(args, work / dt, dt * 1e3, config)
+    # the same instances solved one after another by the single-instance
+    # fused solver (no batching), at equal T and N
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Fs = []
+    for p in probs:
+        r1 = fr.solve(ctx, p, N, lr, want_X=False)
+        Fs.append(r1["F_hist"].cpu().numpy())
+        del r1
+    torch.cuda.synchronize()
+    sdt = time.perf_counter() - t0
+    out["sequential_fused"] = {"value": work / sdt, "ms_per_step": sdt * 1e3,
+                               "batched_speedup": sdt / dt,
+                               "F_rel_diff_max": float(max(np.max(np.abs(a / b - 1))
+                                                           for a, b in zip(Fb, Fs)))}
+    print(f"bench: sequential fused {sdt:.2f} s", flush=True)
+    if not args.skip_plain:
+        sub = list(range(0, 128, 16))   # 8 instances
+        t0 = time.perf_counter()
+        pwork = 0
+        for j in sub:
+            fr.solve_plain(ctx, probs[j], N, lr, want_X=False)
+            pwork += insts[j].cells * T * N
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        out["plain_gpu"] = {"value": pwork / pdt, "seconds": pdt,
+                            "sample": "instances 0, 16, ..., 112 solved one by one in the "
+                                      "unfused form", "batched_speedup": (work / dt) / (pwork / pdt)}
+        print(f"bench: plain (8 instances) {pdt:.2f} s", flush=True)
+    if not args.skip_cpu:
+        import oracle
+        j = 0
+        x = insts[j]
+        users = W.subsample_users(x.U, 100, seed=41)
+        t0 = time.perf_counter()
+        oracle.solve(x.r[users], x.e, float(x.eps), T, 2, lr=lr)
+        cdt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 100 * x.I * x.m * T * 2 / cdt, "unit": "cell-iters/s",
+                               "cores": oracle.num_threads(), "kind": "oracle", "seconds": cdt,
+                               "sample": f"100 consumers of instance 0 (I={x.I}, m={x.m}), 2 "
+                                         "outer steps plus the final forward; FP64"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--outer", type=int, default=2, help="outer steps of the C5 solve")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-diag", action="store_true")
@@ -87,6 +418,11 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the consumer-sharded multi-GPU design is described, not built).", flush=True)
         sys.exit(2)
+    heavy = args.workload in ("C4", "C5")
+    if args.steps is None:
+        args.steps = 1 if heavy else 5
+    if args.warmup is None:
+        args.warmup = 0 if heavy else 1
 
     import torch
     import paper_2406_10262_amd as fr
@@ -106,137 +442,14 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "ms": ms.value,
                           "GBps": 2 * nbytes / ms.value / 1e6}), flush=True)
         return
-
-    inst = workload(args.workload)
-    U, I, m, T, N = inst.U, inst.I, inst.m, inst.T, inst.N
-    cells = U * I * m
-    work = cells * T * N            # counted forward cell-iterations per solve
-    ctx = fr.Context(0)
-    prob = fr.Problem(torch.from_numpy(inst.r).to(dev), torch.from_numpy(inst.e).to(dev),
-                      float(inst.eps), T)
-    lr = float(inst.lr)
-    print(f"bench: workload {inst.name} U={U} I={I} m={m} T={T} N={N} "
-          f"launch={ctx.get_launch(I, m)}", flush=True)
-
-    for _ in range(args.warmup):
-        res = fr.solve(ctx, prob, N, lr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = fr.solve(ctx, prob, N, lr)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    value = work * args.steps / dt
-    print(f"bench: fused {ms_per_step:.2f} ms/solve, {value:.4e} cell-iters/s", flush=True)
-    if args.profile:
-        return
-
-    Fh = res["F_hist"].cpu().numpy()
-    nsw = {"F_0": float(Fh[0]), "F_N": float(Fh[-1])}
-    gold = os.path.join(ROOT, "tests", "golden", f"{inst.name.lower()}_trajectory.json")
-    if os.path.exists(gold):
-        with open(gold) as fh:
-            ref = np.array(json.load(fh)["F_hist"])
-        nsw["rel_err_max"] = float(np.max(np.abs(Fh / ref - 1)))
-        nsw["rel_err_final"] = float(abs(Fh[-1] / ref[-1] - 1))
-        nsw["reference"] = "FP64 oracle trajectory, tests/golden"
-
-    # per-kernel timing with HIP events on the solve's stream
-    lib.fr_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    lib.fr_ctx_kernel_times.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
-    lib.fr_ctx_set_timing(ctx.handle, 1)
-    fr.solve(ctx, prob, N, lr)
-    torch.cuda.synchronize()
-    fms, fn, bms, bn = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
-    lib.fr_ctx_kernel_times(ctx.handle, ctypes.byref(fms), ctypes.byref(fn), ctypes.byref(bms),
-                            ctypes.byref(bn))
-    lib.fr_ctx_set_timing(ctx.handle, 0)
-    fwd_ms = fms.value / max(fn.value, 1)
-    bwd_ms = bms.value / max(bn.value, 1)
-    per_launch = cells * (T + 1)      # cell-iterations of one launch (incl. plan / init pass)
-    kernels = {
-        "k_fwd": {"avg_ms": fwd_ms, "launches": fn.value,
-                  "slots": per_launch * FWD_SLOTS,
-                  "cell_iters_per_s": per_launch / (fwd_ms * 1e-3)},
-        "k_bwd": {"avg_ms": bwd_ms, "launches": bn.value,
-                  "slots": per_launch * BWD_SLOTS,
-                  "cell_iters_per_s": per_launch / (bwd_ms * 1e-3)},
-    }
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
-    dk = kernels[dom]
-    achieved = dk["slots"] / (dk["avg_ms"] * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_SLOTS / 1e12,
-            "unit": "T VALU lane-slots/s", "frac": achieved * 1e12 / PEAK_SLOTS,
-            "traffic": load_traffic(dom, inst.name),
-            "avg_launch_ms": dk["avg_ms"],
-            "model": f"{BWD_SLOTS if dom == 'k_bwd' else FWD_SLOTS} non-transcendental VALU "
-                     "lane-slots per cell-iteration (the exponential overlaps on its own "
-                     "half-rate pipe), U*I*m*(T+1) cell-iterations per launch; peak = 256 CUs "
-                     "x 64 lanes x 2.4 GHz"}
-    print(f"bench: kernels fwd {fwd_ms:.3f} ms bwd {bwd_ms:.3f} ms per launch", flush=True)
-
-    out = {
-        "metric": "plan-cells·Sinkhorn-iters/s", "value": value, "unit": "cell-iters/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{inst.name}: U={U} consumers, I={I} items, m={m} positions "
-                               f"(incl. dummy), low-rank-16 sigmoid relevance, e_k=1/log2(k+1), "
-                               f"eps={float(inst.eps)}, T={T} Sinkhorn iterations, N={N} Adam "
-                               f"steps (lr=0.1 eps), FP32 plans, FP64 impacts and log-NSW",
-                   "step": "one full solve (N outer steps + final forward)",
-                   "cells": cells, "cell_iters_per_step": work},
-        "nsw": nsw,
-        "kernels": {k: {"avg_ms": v["avg_ms"], "launches": v["launches"],
-                        "cell_iters_per_s": v["cell_iters_per_s"]} for k, v in kernels.items()},
-        "roofline": roof,
-    }
-
-    if not args.skip_diag:
-        lib.fr_diag_alu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
-        diag = {}
-        for kind, name in ((0, "exp2_per_s"), (1, "fma_per_s"), (2, "exp_plus_5fma_per_s")):
-            ms, ops = ctypes.c_double(), ctypes.c_double()
-            rc = lib.fr_diag_alu(kind, 256 * 32, 2000, ctypes.byref(ms), ctypes.byref(ops))
-            if rc == 0:
-                diag[name] = ops.value / (ms.value * 1e-3)
-        out["measured_peaks"] = diag
-
-    if not args.skip_plain:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pres = fr.solve_plain(ctx, prob, N, lr)
-        torch.cuda.synchronize()
-        pdt = time.perf_counter() - t0
-        pF = pres["F_hist"].cpu().numpy()
-        out["plain_gpu"] = {
-            "value": work / pdt, "ms_per_step": pdt * 1e3,
-            "fused_speedup": (work / (ms_per_step * 1e-3)) / (work / pdt),
-            "F_N": float(pF[-1]),
-            "F_rel_diff_vs_fused": float(np.max(np.abs(pF / Fh - 1))),
-            "form": "one kernel launch per Sinkhorn half-iteration, potentials of every "
-                    "iteration in HBM, reverse sweep reading them back, no graph"}
-        if "rel_err_max" in nsw:
-            out["plain_gpu"]["rel_err_max"] = float(np.max(np.abs(pF / ref - 1)))
-        print(f"bench: plain {pdt * 1e3:.1f} ms/solve", flush=True)
-
-    if not args.skip_cpu:
-        import oracle
-        Ns = 2
-        t0 = time.perf_counter()
-        oracle.solve(inst.r, inst.e, float(inst.eps), T, Ns, lr=lr)
-        cdt = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": cells * T * Ns / cdt, "unit": "cell-iters/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": cdt,
-            "sample": f"full {inst.name} instance, {Ns} of its {N} outer steps (each a T={T} "
-                      f"forward, gradient and Adam update) plus the final forward; FP64, "
-                      f"OpenMP over consumers"}
-        print(f"bench: oracle {cdt:.1f} s for {Ns} steps", flush=True)
-
-    print(json.dumps(out), flush=True)
+    if args.workload == "C3":
+        out = bench_grad(args, fr, lib, dev)
+    elif args.workload == "C4":
+        out = bench_batched(args, fr, lib, dev)
+    else:
+        out = bench_solve(args, fr, lib, dev, args.workload)
+    if out is not None:
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

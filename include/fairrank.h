@@ -192,6 +192,18 @@ fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes,
 fr_status fr_get_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t* lanes,
                         int32_t* rows_per_lane);
 
+/* Autotuner: times every instantiated launch shape (lanes, rows per lane)
+ * that covers the problem's I rows, running the fused forward, the impact
+ * reduction and the fused backward on this problem and cost tensor C with
+ * min(T, iters) Sinkhorn iterations (HIP events on the stream; synchronises),
+ * and keeps the fastest for (I, m) in the context.  batched != 0 restricts the
+ * search to shapes the batched kernels accept (teams of at most 256 lanes).
+ * Needs the workspace of fr_workspace_bytes.  The choice is written to
+ * *lanes_out, *rows_out (host, optional). */
+fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32_t batched,
+                      int32_t iters, void* ws, size_t ws_bytes, void* stream, int32_t* lanes_out,
+                      int32_t* rows_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,13 +86,15 @@ def load():
     lib.fr_solve_plain.argtypes = [P, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_sync_status.argtypes = [P, P, P]
     lib.fr_workspace_bytes_batched.argtypes = [I32, PP, PO, ctypes.POINTER(SZ)]
+    lib.fr_autotune.argtypes = [P, PP, P, I32, I32, P, SZ, P, ctypes.POINTER(I32),
+                                ctypes.POINTER(I32)]
     lib.fr_solve_batched.argtypes = [P, I32, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_get_launch.argtypes = [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
-                 "fr_workspace_bytes_batched", "fr_solve_batched",
+                 "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
                  "fr_set_launch", "fr_get_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -146,6 +148,20 @@ class Context:
 
     def set_launch(self, n_items: int, m: int, lanes: int, rows: int):
         _check(load().fr_set_launch(self.handle, n_items, m, lanes, rows), "fr_set_launch")
+
+    def autotune(self, prob: "Problem", C: Optional[torch.Tensor] = None, batched: bool = False,
+                 iters: int = 16):
+        """Times the launch shapes on this problem and keeps the fastest."""
+        if C is None:
+            C = torch.zeros((prob.U, prob.I, prob.m), dtype=torch.float32, device=self.device)
+        _f32(C, (prob.U, prob.I, prob.m), "C")
+        ws = self.workspace(workspace_bytes(prob, 1))
+        L, R = ctypes.c_int32(), ctypes.c_int32()
+        p = prob.c()
+        _check(load().fr_autotune(self.handle, ctypes.byref(p), _ptr(C), int(batched), int(iters),
+                                  _ptr(ws), ws.numel(), _stream(self.device), ctypes.byref(L),
+                                  ctypes.byref(R)), "fr_autotune")
+        return L.value, R.value
 
     def get_launch(self, n_items: int, m: int):
         L, R = ctypes.c_int32(), ctypes.c_int32()

@@ -340,7 +340,7 @@ fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
     if (mp < 0) return FR_E_UNSUPPORTED;
     const int BL = (K <= 1) ? kLoadBlock : K;
     auto fits = [&](int L, int R, const FusedEntry** fe_out, size_t* lf, size_t* lb) {
-        if (!lanes_ok(L) || L > 256 || (int64_t)L * R < I) return false;
+        if (!lanes_ok(L) || L > 256 || 256 % L != 0 || (int64_t)L * R < I) return false;
         const FusedEntry* fe = reg.find(mp, R, 256);
         if (!fe) return false;
         const int W = (L + 63) / 64;
@@ -1008,6 +1008,80 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     forward_phase(dff);
     FR_TRY(hipGetLastError());
     return read_flags(hdr, s, false);
+}
+
+fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32_t batched,
+                      int32_t iters, void* ws, size_t ws_bytes, void* stream, int32_t* lanes_out,
+                      int32_t* rows_out) {
+    if (!ctx || !C || !ws) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (iters < 1) return FR_E_PARAM;
+    fr_problem p = *prob;
+    p.sinkhorn_iters = std::min(prob->sinkhorn_iters, iters);
+    const Layout Lw = layout(&p, 1);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    const Registry& reg = registry();
+    const int mp = reg.mp_for(p.m);
+    if (mp < 0) return FR_E_UNSUPPORTED;
+    const int I = p.n_items;
+    const auto saved = ctx->launch;
+    hipEvent_t e0, e1;
+    FR_TRY(hipEventCreate(&e0));
+    FR_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::pair<int, int> best_lr{0, 0};
+    const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024};
+    for (int L : Ls) {
+        if (batched && (L > 256 || 256 % L != 0)) continue;
+        for (auto& e : reg.all) {
+            if (e.mp != mp) continue;
+            const int R = e.rows;
+            if ((int64_t)L * R < I || (int64_t)L * (R - 1) >= I) continue;
+            if ((e.lb == 256) != (L <= 256)) continue;
+            if (batched && R * mp > 128) continue;
+            ctx->launch[{I, p.m}] = {L, R};
+            Shape sh;
+            if (make_shape(ctx, p.n_users, I, p.m, 1, &sh) != FR_OK) continue;
+            if (sh.fe != &e) continue;
+            FwdArgs a = fwd_args(&p, sh, C);
+            a.y = (float*)(w + Lw.y);
+            a.hist = (float*)(w + Lw.hist);
+            a.nck = Lw.nck;
+            BwdArgs b = bwd_args(&p, sh, C);
+            b.hist = a.hist;
+            b.nck = Lw.nck;
+            double* impw = (double*)(w + Lw.imp);
+            b.imp = impw;
+            float tot = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+                FR_TRY(hipEventRecord(e0, s));
+                sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+                launch_impact(a.y, p.n_users, I, (double*)(w + Lw.partial), Lw.nchunk, impw,
+                              nullptr, nullptr, 0, (WsHeader*)(w + Lw.hdr), 0, s);
+                sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+                FR_TRY(hipEventRecord(e1, s));
+                FR_TRY(hipEventSynchronize(e1));
+                FR_TRY(hipGetLastError());
+                FR_TRY(hipEventElapsedTime(&tot, e0, e1));
+            }
+            if (tot < best) {
+                best = tot;
+                best_lr = {L, R};
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->launch = saved;
+    if (best_lr.first == 0) return FR_E_UNSUPPORTED;
+    ctx->launch[{I, p.m}] = best_lr;
+    if (lanes_out) *lanes_out = best_lr.first;
+    if (rows_out) *rows_out = best_lr.second;
+    return FR_OK;
 }
 
 }  // extern "C"

@@ -170,7 +170,8 @@ template <int MP, int R>
 __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int64_t u = u_first + tm.team;
-    const bool active = u < a.U;
+    // lanes past the last whole team of the block own no consumer
+    const bool active = tm.team < (int)(blockDim.x / a.L) && u < a.U;
     const int I = a.I, m = a.m;
     float* red = smem + tm.team * (2 * tm.W * MP);
 
@@ -250,7 +251,7 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     const Team tm = make_team(a.L);
     const int teams = blockDim.x / a.L;
     const int64_t u = u_first + tm.team;
-    const bool active = u < a.U;
+    const bool active = tm.team < teams && u < a.U;
     const int I = a.I, m = a.m;
     const int BL = (a.K == 1) ? kLoadBlock : a.K;
     float* seg = smem + tm.team * ((BL + 1) * MP);

@@ -17,7 +17,13 @@ the GPU library.
                      sampled consumers, and FP64 central differences
                      (h = 1e-4) at 64 cost and 64 relevance coordinates.
 
-Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3]
+  c5_sub.npz         1000 consumers sampled (seed 55) from the 100000 x 1000 x 50
+                     workload (eps 0.01, T 300): at C ~ N(0, (2 eps)^2) (seed 56)
+                     the oracle's impacts and F of the sub-instance and the
+                     plans of two of its consumers; and Algorithm 1 (Adam,
+                     lr 0.1 eps) for 3 steps from C = 0: F_0..F_3.
+
+Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3] [c5]
 """
 import json
 import os
@@ -143,6 +149,34 @@ def c3():
     np.savez_compressed(os.path.join(HERE, "c3_grad.npz"), **out)
 
 
+def c5_subsample():
+    """The 1000-consumer sub-instance of the precision-at-scale workload."""
+    inst = W.config("C5")
+    users = W.subsample_users(inst.U, 1000, seed=55)
+    return inst, users, inst.r[users]
+
+
+def c5():
+    inst, users, r = c5_subsample()
+    I, m, T = inst.I, inst.m, inst.T
+    eps = float(inst.eps)
+    rs = r.astype(np.float64)
+    e = inst.e.astype(np.float64)
+    t0 = time.time()
+    C = W.random_costs(1000, I, m, 2 * eps, seed=56)
+    X = oracle.forward(C, eps, T)
+    imp = oracle.impact(rs, e, X)
+    F = oracle.nsw(imp)
+    X2 = X[[0, 777]].astype(np.float32)
+    del X
+    print("c5 forward", time.time() - t0, F, flush=True)
+    res = oracle.solve(rs, e, eps, T, 3, lr=float(inst.lr))
+    print("c5 solve", time.time() - t0, res["F_hist"], flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_sub.npz"), users=users, rand_imp=imp,
+                        rand_F=np.array([F]), rand_X_sel=X2, sel=np.array([0, 777]),
+                        adam_F_hist=res["F_hist"], adam_imp=res["imp"])
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["tiny"]
     if "tiny" in which:
@@ -151,3 +185,5 @@ if __name__ == "__main__":
         c2()
     if "c3" in which:
         c3()
+    if "c5" in which:
+        c5()

@@ -150,3 +150,16 @@ def test_solve_C2_matches_oracle_trajectory(fr, ctx):
     imp = prob_out[0].cpu().numpy()
     print("C2 final impacts rel err", np.max(np.abs(imp / imp_ref - 1)), flush=True)
     assert np.max(np.abs(imp / imp_ref - 1)) <= 1e-5
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_parity(fr):
+    ctx = fr.Context(0)
+    inst = W.config("C1")
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    L, R = ctx.autotune(prob)
+    assert ctx.get_launch(inst.I, inst.m) == (L, R) and L * R >= inst.I
+    Lb, Rb = ctx.autotune(prob, batched=True)
+    assert Lb <= 256 and Lb * Rb >= inst.I
+    res = fr.solve(ctx, prob, 5, float(inst.lr))
+    ref = oracle.solve(inst.r, inst.e, float(inst.eps), inst.T, 5, lr=float(inst.lr))
+    assert np.max(np.abs(res["F_hist"].cpu().numpy() / ref["F_hist"] - 1)) <= F_REL

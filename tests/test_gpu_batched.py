@@ -85,3 +85,17 @@ def test_batched_gradient_ascent_matches_oracle(fr, j):
     assert np.max(np.abs(res[j]["X"].double().cpu().numpy() - ref["X"])) <= 1e-5
     Cref = ref["C"]
     assert np.max(np.abs(res[j]["C"].double().cpu().numpy() - Cref)) <= 1e-5 * np.max(np.abs(Cref))
+
+
+def test_batched_ignores_team_widths_that_do_not_tile_its_blocks(fr):
+    """A 192-lane team does not divide the batched kernels' 256-thread blocks;
+    the batched path must fall back to a tiling shape (it once ran a phantom
+    partial team on such a request)."""
+    x = W.batched_instance(19, (300, 319, 41), T=30, N=2)
+    ctx = fr.Context(0)
+    ctx.set_launch(x.I, x.m, 192, 2)
+    p = device_problem(fr, x.r, x.e, x.eps, x.T)
+    b = fr.solve_batched(ctx, [p], 2, 0.003)
+    one = fr.solve(ctx, p, 2, 0.003)
+    Fb, Fs = b[0]["F_hist"].cpu().numpy(), one["F_hist"].cpu().numpy()
+    assert np.all(np.isfinite(Fb)) and np.max(np.abs(Fb / Fs - 1)) <= 1e-7
