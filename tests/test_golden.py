@@ -45,3 +45,14 @@ def test_c2_trajectory_is_an_ascent_from_the_uniform_policy():
     Fh = np.array(g["F_hist"])
     assert abs(Fh[0] - F0) < 1e-9 * abs(F0)
     assert len(Fh) == inst.N + 1 and Fh[-1] > Fh[0]
+
+
+def test_c5_subsample_golden_is_an_ascent():
+    d = np.load(os.path.join(GOLDEN, "c5_sub.npz"))
+    Fh = d["adam_F_hist"]
+    assert len(Fh) == 4 and np.all(np.diff(Fh) > 0)
+    assert d["users"].shape == (1000,) and np.all(np.diff(d["users"]) > 0)
+    X = d["rand_X_sel"].astype(np.float64)
+    b = np.ones(50)
+    b[-1] = 1000 - 50 + 1
+    assert np.max(np.abs(X.sum(1) - b[None]) / b[None]) < 1e-6   # float32-stored columns
