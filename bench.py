@@ -142,9 +142,10 @@ def bench_solve(args, fr, lib, dev, name):
                       float(inst.eps), T)
     lr = float(inst.lr)
     if args.autotune:
-        ctx.autotune(prob)
+        # all T iterations for the small workloads; a short run on the large one
+        ctx.autotune(prob, iters=T if name != "C5" else 20)
     print(f"bench: workload {inst.name} U={U} I={I} m={m} T={T} N={N} "
-          f"launch={ctx.get_launch(I, m)}", flush=True)
+          f"launch={ctx.get_launch(U, I, m)}", flush=True)
     for _ in range(args.warmup):
         res = fr.solve(ctx, prob, N, lr, x_dtype=x_dtype)
     torch.cuda.synchronize()
@@ -335,7 +336,7 @@ def bench_batched(args, fr, lib, dev):
         for p in probs:
             if (p.I, p.m) not in seen:
                 seen.add((p.I, p.m))
-                ctx.autotune(p, batched=True)
+                ctx.autotune(p, batched=True, iters=16)
     print(f"bench: workload C4 128 instances, {cells:.3e} cells, T={T}, N={N}", flush=True)
     for _ in range(args.warmup):
         res = fr.solve_batched(ctx, probs, N, lr, want_X=False)

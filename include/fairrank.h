@@ -186,10 +186,13 @@ const char* fr_status_string(fr_status s);
 /* Launch configuration of the fused kernels for plans of a given shape:
  * lanes per consumer (1..64 as a power of two, or a multiple of 64 up to
  * 1024) and plan rows held by each lane.  fr_set_launch overrides the
- * library's choice for (I, m); fr_get_launch reports the current choice. */
+ * library's choice for (I, m) (FR_E_UNSUPPORTED if no kernel is instantiated
+ * for it); fr_get_launch reports the shape a problem of n_users consumers
+ * and this (I, m) runs with: the override if one is set, else the library's
+ * choice from its issue model, which depends on n_users. */
 fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes,
                         int32_t rows_per_lane);
-fr_status fr_get_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t* lanes,
+fr_status fr_get_launch(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m, int32_t* lanes,
                         int32_t* rows_per_lane);
 
 /* Autotuner: times every instantiated launch shape (lanes, rows per lane)

@@ -91,7 +91,7 @@ def load():
     lib.fr_solve_batched.argtypes = [P, I32, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
-    lib.fr_get_launch.argtypes = [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
@@ -150,8 +150,11 @@ class Context:
         _check(load().fr_set_launch(self.handle, n_items, m, lanes, rows), "fr_set_launch")
 
     def autotune(self, prob: "Problem", C: Optional[torch.Tensor] = None, batched: bool = False,
-                 iters: int = 16):
-        """Times the launch shapes on this problem and keeps the fastest."""
+                 iters: Optional[int] = None):
+        """Times the launch shapes on this problem (min(T, iters) Sinkhorn
+        iterations; all T by default) and keeps the fastest."""
+        if iters is None:
+            iters = prob.T
         if C is None:
             C = torch.zeros((prob.U, prob.I, prob.m), dtype=torch.float32, device=self.device)
         _f32(C, (prob.U, prob.I, prob.m), "C")
@@ -163,10 +166,11 @@ class Context:
                                   ctypes.byref(R)), "fr_autotune")
         return L.value, R.value
 
-    def get_launch(self, n_items: int, m: int):
+    def get_launch(self, n_users: int, n_items: int, m: int):
+        """(lanes, rows per lane) a problem of this shape runs with."""
         L, R = ctypes.c_int32(), ctypes.c_int32()
-        _check(load().fr_get_launch(self.handle, n_items, m, ctypes.byref(L), ctypes.byref(R)),
-               "fr_get_launch")
+        _check(load().fr_get_launch(self.handle, n_users, n_items, m, ctypes.byref(L),
+                                    ctypes.byref(R)), "fr_get_launch")
         return L.value, R.value
 
 

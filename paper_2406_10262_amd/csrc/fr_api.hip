@@ -61,10 +61,15 @@ struct Registry {
             if (e.mp >= m && e.mp < best) best = e.mp;
         return best == (1 << 30) ? -1 : best;
     }
-    const FusedEntry* find(int mp, int rows, int lb) const {
+    const FusedEntry* find(int mp, int rows, int lb, bool wide) const {
         for (auto& e : all)
-            if (e.mp == mp && e.rows == rows && e.lb == lb) return &e;
+            if (e.mp == mp && e.rows == rows && e.lb == lb && e.wide == wide) return &e;
         return nullptr;
+    }
+    // Kernel for teams of L lanes in blocks of `block` threads.
+    const FusedEntry* pick(int mp, int rows, int L, int block) const {
+        const int lb = block <= 256 ? 256 : (block <= 512 ? 512 : 1024);
+        return find(mp, rows, lb, L >= 64);
     }
 };
 
@@ -78,6 +83,10 @@ bool lanes_ok(int L) {
     return L > 64 && L <= 1024 && L % 64 == 0;
 }
 
+// Threads per block for teams of L lanes: several teams of up to one wave
+// share a 256-thread block; larger teams take a block each.
+int block_for(int L) { return L <= 64 ? 256 : L; }
+
 // Launch shape of the fused kernels for one problem.
 struct Shape {
     const FusedEntry* fe;
@@ -85,21 +94,31 @@ struct Shape {
     size_t lds_fwd, lds_bwd;
 };
 
-// Lane-cycle model of one Sinkhorn iteration per consumer: R*MP cells per
-// lane at ~9 issue slots (one quarter-rate exponential plus five full-rate
-// ops) plus the column reduction (log2 L butterfly steps per column, an LDS
-// exchange across waves) and the column update.
-double model_cost(int I, int mp, int L, int R) {
-    (void)I;
-    const double cell = 9.0 * R * mp;
-    const double steps = (double)std::min(6, (int)ceil(log2((double)std::min(L, 64)) - 1e-9));
-    double red = mp * steps;
-    if (L > 64) red += 2.0 * mp + 40.0;
-    double upd = (L >= 64) ? 2.0 * mp + 4.0 : 4.0 * mp;
-    return (double)L * (cell + red + upd);
+// Issue model of one Sinkhorn iteration (forward and backward) of U consumers
+// with teams of L lanes and R rows per lane.  A wave issues R*MP cells at ~13
+// VALU operations (~18 when the kernel recomputes the exponentials), plus the
+// column reduction and update: per column log2 L butterfly steps and the
+// update for teams narrower than a wave, ~4 operations per column for the
+// reduce-scatter of wave-wide teams, plus an LDS exchange for teams of
+// several waves.  Each of the 1024 SIMDs runs its share of the waves back to
+// back, and a SIMD with a single wave hides its latencies poorly.
+double model_cost(int64_t U, int mp, int L, const FusedEntry& e) {
+    const double cell = (e.recomp_f ? 7.0 : 5.0) + (e.recomp_b ? 11.0 : 8.0);
+    double red;
+    if (L < 64) {
+        int lv = 0;
+        while ((1 << lv) < L) ++lv;
+        red = 2.0 * mp * (std::min(lv, 4) + (L > 16 ? 2 : 0) + 3.0);
+    } else {
+        red = 2.0 * (4.0 * mp + 10.0) + mp + (L > 64 ? 2.0 * (40.0 + L / 64) : 0.0);
+    }
+    const double per_wave = e.rows * mp * cell + red;
+    const double waves = (double)U * (L < 64 ? L / 64.0 : (double)(L / 64));
+    const double per_simd = waves / 1024.0;
+    return std::max(1.0, per_simd) * per_wave * (per_simd <= 1.0 ? 1.25 : 1.0);
 }
 
-std::pair<int, int> default_launch(int I, int m) {
+std::pair<int, int> default_launch(int64_t U, int I, int m) {
     const Registry& reg = registry();
     const int mp = reg.mp_for(m);
     double best = 1e300;
@@ -111,12 +130,10 @@ std::pair<int, int> default_launch(int I, int m) {
             if (e.mp != mp) continue;
             const int R = e.rows;
             if ((int64_t)L * R < I) continue;
-            if (e.lb == 256 && L > 256) continue;
-            if (e.lb == 1024 && L <= 256) continue;
-            if (R * mp > 64) continue;  // keep the backward's share within registers
+            if (&e != reg.pick(mp, R, L, block_for(L))) continue;
             // no more lanes than rows need
             if ((int64_t)L * (R - 1) >= I) continue;
-            const double c = model_cost(I, mp, L, R);
+            const double c = model_cost(U, mp, L, e);
             if (c < best) {
                 best = c;
                 out = {L, R};
@@ -132,12 +149,11 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     if (mp < 0) return FR_E_UNSUPPORTED;
     std::pair<int, int> lr;
     auto it = ctx->launch.find({I, m});
-    lr = (it != ctx->launch.end()) ? it->second : default_launch(I, m);
+    lr = (it != ctx->launch.end()) ? it->second : default_launch(U, I, m);
     const int L = lr.first, R = lr.second;
     if (!lanes_ok(L) || (int64_t)L * R < I) return FR_E_PARAM;
-    int block = (L <= 64) ? 256 : L;
-    const int lb = (block <= 256) ? 256 : 1024;
-    const FusedEntry* fe = reg.find(mp, R, lb);
+    int block = block_for(L);
+    const FusedEntry* fe = reg.pick(mp, R, L, block);
     if (!fe) return FR_E_UNSUPPORTED;
     const int W = (L + 63) / 64;
     const int BL = (K <= 1) ? kLoadBlock : K;
@@ -174,7 +190,7 @@ Layout layout(const fr_problem* p, int K) {
     const int I = p->n_items;
     L.nchunk = impact_chunks(U, I);
     L.nck = n_checkpoints(p->sinkhorn_iters, K);
-    L.hs = p->m;
+    L.hs = registry().mp_for(p->m);   // potentials padded to the column class
     size_t off = 0;
     L.hdr = off;
     off += align_up(sizeof(WsHeader));
@@ -262,7 +278,7 @@ FwdArgs fwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     a.T = p->sinkhorn_iters;
     a.K = 1;
     a.nck = 0;
-    a.hs = p->m;
+    a.hs = registry().mp_for(p->m);
     a.L = sh.L;
     a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
     a.eps_ln2 = (float)((double)p->eps * M_LN2);
@@ -278,7 +294,7 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     a.I = p->n_items;
     a.m = p->m;
     a.T = p->sinkhorn_iters;
-    a.hs = p->m;
+    a.hs = registry().mp_for(p->m);
     a.L = sh.L;
     a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
     a.inv_eps = (float)(1.0 / (double)p->eps);
@@ -341,7 +357,7 @@ fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
     const int BL = (K <= 1) ? kLoadBlock : K;
     auto fits = [&](int L, int R, const FusedEntry** fe_out, size_t* lf, size_t* lb) {
         if (!lanes_ok(L) || L > 256 || 256 % L != 0 || (int64_t)L * R < I) return false;
-        const FusedEntry* fe = reg.find(mp, R, 256);
+        const FusedEntry* fe = reg.pick(mp, R, L, 256);
         if (!fe) return false;
         const int W = (L + 63) / 64;
         const int teams = 256 / L;
@@ -366,13 +382,14 @@ fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
     const int Ls[] = {8, 16, 32, 64, 128, 256};
     for (int L : Ls) {
         for (auto& e : reg.all) {
-            if (e.mp != mp || e.lb != 256) continue;
+            if (e.mp != mp || e.lb != 256 || e.wide != (L >= 64)) continue;
             const int R = e.rows;
             if ((int64_t)L * (R - 1) >= I) continue;
             const FusedEntry* fe;
             size_t lf, lb;
             if (!fits(L, R, &fe, &lf, &lb)) continue;
-            const double c = model_cost(I, mp, L, R) * (R * mp > 64 ? 1.5 : 1.0);
+            // the batch as a whole fills the device: cost in the saturated regime
+            const double c = model_cost((int64_t)1 << 20, mp, L, *fe);
             if (c < best) {
                 best = c;
                 *bs = BatchShape{fe, L, R, mp, 256 / L, lf, lb};
@@ -418,7 +435,7 @@ fr_status plan_batch(fr_ctx* ctx, int n, const fr_problem* probs, int K, BatchPl
         b.y = off;
         off += align_up(sizeof(float) * (size_t)p.n_users * p.n_items);
         b.hist = off;
-        off += align_up(sizeof(float) * (size_t)p.n_users * b.nck * p.m);
+        off += align_up(sizeof(float) * (size_t)p.n_users * b.nck * b.sh.mp);
     }
     // classes and items
     P->classes.clear();
@@ -565,17 +582,19 @@ fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes, 
     if (!lanes_ok(lanes) || rows < 1 || (int64_t)lanes * rows < n_items) return FR_E_PARAM;
     const Registry& reg = registry();
     const int mp = reg.mp_for(m);
-    const int lb = (lanes <= 256) ? 256 : 1024;
-    if (!reg.find(mp, rows, lb)) return FR_E_UNSUPPORTED;
+    if (!reg.pick(mp, rows, lanes, block_for(lanes))) return FR_E_UNSUPPORTED;
     ctx->launch[{n_items, m}] = {lanes, rows};
     return FR_OK;
 }
 
-fr_status fr_get_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t* lanes, int32_t* rows) {
+fr_status fr_get_launch(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m, int32_t* lanes,
+                        int32_t* rows) {
     if (!ctx || !lanes || !rows) return FR_E_NULL;
     if (n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems) return FR_E_SHAPE;
     auto it = ctx->launch.find({n_items, m});
-    std::pair<int, int> lr = (it != ctx->launch.end()) ? it->second : default_launch(n_items, m);
+    if (n_users < 1) return FR_E_SHAPE;
+    std::pair<int, int> lr =
+        (it != ctx->launch.end()) ? it->second : default_launch(n_users, n_items, m);
     *lanes = lr.first;
     *rows = lr.second;
     return FR_OK;
@@ -1041,7 +1060,7 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             if (e.mp != mp) continue;
             const int R = e.rows;
             if ((int64_t)L * R < I || (int64_t)L * (R - 1) >= I) continue;
-            if ((e.lb == 256) != (L <= 256)) continue;
+            if (&e != reg.pick(mp, R, L, batched ? 256 : block_for(L))) continue;
             if (batched && R * mp > 128) continue;
             ctx->launch[{I, p.m}] = {L, R};
             Shape sh;
@@ -1056,8 +1075,9 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             b.nck = Lw.nck;
             double* impw = (double*)(w + Lw.imp);
             b.imp = impw;
-            float tot = 0.f;
-            for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+            // one warm-up repetition, then the fastest of three
+            float tot = 1e30f;
+            for (int rep = 0; rep < 4; ++rep) {
                 FR_TRY(hipEventRecord(e0, s));
                 sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
                 launch_impact(a.y, p.n_users, I, (double*)(w + Lw.partial), Lw.nchunk, impw,
@@ -1066,7 +1086,9 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
                 FR_TRY(hipEventRecord(e1, s));
                 FR_TRY(hipEventSynchronize(e1));
                 FR_TRY(hipGetLastError());
-                FR_TRY(hipEventElapsedTime(&tot, e0, e1));
+                float ms = 0.f;
+                FR_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) tot = std::min(tot, ms);
             }
             if (tot < best) {
                 best = tot;

@@ -8,18 +8,31 @@
 // plan rows i = l + j*L (j < R) and keeps their m costs in registers for the
 // whole kernel, so the T Sinkhorn iterations (Section 3, problem otp) never
 // touch HBM.  The row half-step (softmax over the m positions of a row) is
-// lane-local; the column half-step needs the sum over the team's rows, done
-// with DPP/permlane butterflies inside a wave and, for teams of several
-// waves, one LDS exchange per half-step.
+// lane-local; the column half-step needs the sum over the team's rows.
 //
 // Arithmetic.  Log-domain, base 2: with gamma_k = g_k / (eps ln 2) and the
 // cost exponent z_ik = -c_ik / (eps ln 2) + gamma_k (one FMA), one iteration is
-//   P_ik   = 2^(z_ik - M_i) / s_i          (row softmax, M_i the row max)
+//   P_ik   = 2^(z_ik - S_i) / s_i,  s_i = sum_k 2^(z_ik - S_i)   (row softmax)
 //   sig_k  = sum_i P_ik
 //   gamma_k += log2 b_k - log2 sig_k        (b = 1 ... 1, I-m+1)
 // which is the textbook pair of LSE half-steps with a single exponential per
-// cell.  The plan is X_ik = 2^(z^T_ik + phi_i), phi_i = -(M_i + log2 s_i) from
+// cell.  The plan is X_ik = 2^(z^T_ik + phi_i), phi_i = -(S_i + log2 s_i) from
 // the last row half-step.
+//
+// Row shift.  Any S_i gives the same P as long as 2^(z - S_i) stays in range.
+// The first row half-step uses the exact row maximum; later ones reuse the
+// row's log-sum-exp from the previous half-step, which moves only by the
+// change of the column potentials, and so skip the max pass.  A row whose sum
+// s_i leaves [2^-16, 2^16] (or is not finite) is redone with its exact max.
+//
+// Column sums.  Teams narrower than a wave all-reduce every column with DPP
+// row butterflies and the gfx950 row swaps.  Teams of whole waves use a
+// reduce-scatter instead: v_permlane32_swap and v_permlane16_swap each halve
+// the columns a lane carries (columns are taken in chunks of 16), DPP row
+// butterflies finish the sums inside 16-lane rows, and then each lane owns at
+// most one column.  The owner updates that column's potential and v_readlane
+// broadcasts the potentials as wave-uniform (scalar) operands.  Teams of
+// several waves add the per-wave totals through LDS.
 //
 // Backward (Section 3, "chain rule").  With P^t and the column sums sig^t of
 // iteration t, the adjoints of (f, g) and C run backwards as
@@ -31,6 +44,14 @@
 //   cbar = -G X / eps,  fbar0 = (G X) 1 / eps,  gbar = (G X)^T 1 / eps.
 // Only the column potentials gamma^t are needed to rebuild P^t, so the forward
 // keeps them every K iterations and each segment is recomputed on chip.
+//
+// Register budget.  Kernels whose per-lane state (costs, cost adjoints and one
+// row of exponentials) would not fit the registers of their launch bound
+// recompute the exponentials in a second pass instead of keeping them
+// ("recompute" variants): one pass for the row sums, one that produces the
+// column partials chunk by chunk.
+#include <type_traits>
+
 #include "fr_device.h"
 #include "fr_internal.h"
 
@@ -41,6 +62,25 @@
 namespace fr {
 namespace {
 
+constexpr float kShiftLo = 1.0f / 65536.0f;
+constexpr float kShiftHi = 65536.0f;
+// Floor of a column sum before its logarithm: an empty (padded) column keeps
+// its potential kNeg, since kNeg + 126 rounds back to kNeg.
+constexpr float kTiny = 1.17549435e-38f;
+
+// x, hidden from the optimiser.  Used so that a second pass over a row does
+// not reuse (and keep live) the first pass's products, and so that per-column
+// conditions after the iteration loop are formed there instead of being kept
+// live through it as lane masks.
+__device__ __forceinline__ float opaque(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ int opaque_u(int x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 struct Team {
     int L;      // lanes per consumer
     int lt;     // lane within the team
@@ -48,7 +88,6 @@ struct Team {
     int wt;     // wave within the team
     int W;      // waves per team
     int team;   // team within the block
-    bool wide;  // the team spans at least one whole wave
     bool multi; // the team spans several waves
 };
 
@@ -61,92 +100,346 @@ __device__ __forceinline__ Team make_team(int L) {
     t.lw = tid & 63;
     t.wt = t.lt >> 6;
     t.W = (L + 63) >> 6;
-    t.wide = L >= 64;
     t.multi = L > 64;
     return t;
 }
 
-// Sum acc[k] over the team; every lane ends with the totals.
-template <int MP>
-__device__ __forceinline__ void team_sum(float (&acc)[MP], const Team& tm, float* red, int par) {
-    if (!tm.multi) {
-        group_allreduce<MP>(acc, tm.L);
-        return;
+// ---------------------------------------------------------------------------
+// Reduce-scatter layout of a wave.  Chunk ch covers columns [16 ch, 16 ch + n).
+// The 32-lane swap leaves columns k0 + [0, H1) in the low half and
+// k0 + H1 + [0, n - H1) in the high half; the 16-lane swap splits each half
+// at H2, so 16-lane row rho keeps H2 (even rho) or H1 - H2 (odd rho) columns,
+// in slots q0 .. q0 + H2 - 1 of the row.
+struct ChunkInfo {
+    int k0, n, H1, H2, q0;
+};
+
+constexpr int n_chunks(int MP) { return (MP + 15) / 16; }
+
+constexpr ChunkInfo chunk_info(int MP, int ch) {
+    ChunkInfo c{0, 0, 0, 0, 0};
+    int q0 = 0;
+    for (int i = 0; i <= ch; ++i) {
+        const int k0 = 16 * i;
+        const int n = (MP - k0) < 16 ? (MP - k0) : 16;
+        const int H1 = (n + 1) / 2;
+        const int H2 = (H1 + 1) / 2;
+        c = ChunkInfo{k0, n, H1, H2, q0};
+        q0 += H2;
     }
-    group_allreduce<MP>(acc, 64);
-    const float mine = pick_lane<MP>(acc, tm.lw);
-    float* buf = red + par * (tm.W * MP);
-    if (tm.lw < MP) buf[tm.wt * MP + tm.lw] = mine;
-    __syncthreads();
-    float tot = 0.f;
-    if (tm.lw < MP) {
-        for (int w = 0; w < tm.W; ++w) tot += buf[w * MP + tm.lw];
-    }
-    spread_lanes<MP>(tot, acc);
+    return c;
 }
 
-// Column half-step: gamma_k += log2 b_k - log2 sum_i P_ik.
+constexpr int n_slots(int MP) {
+    return chunk_info(MP, n_chunks(MP) - 1).q0 + chunk_info(MP, n_chunks(MP) - 1).H2;
+}
+static_assert(n_slots(64) <= 16, "one slot per lane of a 16-lane row");
+
+// Lane of the wave that owns column k after the reduce-scatter.
+constexpr int lane_of(int MP, int k) {
+    const ChunkInfo c = chunk_info(MP, k / 16);
+    const int r = k - c.k0;
+    if (r < c.H1) return r < c.H2 ? c.q0 + r : 16 + c.q0 + (r - c.H2);
+    const int s = r - c.H1;
+    return s < c.H2 ? 32 + c.q0 + s : 48 + c.q0 + (s - c.H2);
+}
+
+// Column owned by lane `lane` of a wave (-1 if none); inverse of lane_of.
 template <int MP>
-__device__ __forceinline__ void column_step(float (&acc)[MP], float (&gam)[MP], const float (&lb)[MP],
-                                            int m, const Team& tm, float* red, int par) {
-    if (!tm.wide) {
-        group_allreduce<MP>(acc, tm.L);
+__device__ __forceinline__ int owned_col(int lane) {
+    const int slot = lane & 15;
+    const bool hi = lane >= 32, odd = (lane >> 4) & 1;
+    int col = -1;
 #pragma unroll
-        for (int k = 0; k < MP; ++k) gam[k] = (k < m) ? gam[k] + (lb[k] - lg2(acc[k])) : gam[k];
-        return;
-    }
-    // One logarithm per wave: lane k finishes column k, then spreads it.
-    float tot;
-    if (!tm.multi) {
-        group_allreduce<MP>(acc, 64);
-        tot = pick_lane<MP>(acc, tm.lw);
-    } else {
-        group_allreduce<MP>(acc, 64);
-        const float mine = pick_lane<MP>(acc, tm.lw);
-        float* buf = red + par * (tm.W * MP);
-        if (tm.lw < MP) buf[tm.wt * MP + tm.lw] = mine;
-        __syncthreads();
-        tot = 0.f;
-        if (tm.lw < MP) {
-            for (int w = 0; w < tm.W; ++w) tot += buf[w * MP + tm.lw];
+    for (int ch = 0; ch < n_chunks(MP); ++ch) {
+        const ChunkInfo c = chunk_info(MP, ch);
+        const int j = slot - c.q0;
+        if (j >= 0 && j < c.H2) {
+            const int r = (hi ? c.H1 : 0) + (odd ? c.H2 : 0) + j;
+            const bool ok = (!odd || j < c.H1 - c.H2) && r < c.n;
+            col = ok ? c.k0 + r : -1;
         }
     }
-    const float gmine = pick_lane<MP>(gam, tm.lw);
-    const float lbm = pick_lane<MP>(lb, tm.lw);
-    const float gnew = (tm.lw < m) ? gmine + (lbm - lg2(tot)) : gmine;
-    spread_lanes<MP>(gnew, gam);
+    return col;
 }
 
-// Row half-step for the lane's R rows with column potentials gam.  acc gets
-// the lane's share of the column sums sum_i P_ik; M, s the row max and sum.
+template <int MP, int CH = 0, class F>
+__device__ __forceinline__ void for_chunks(F&& f) {
+    if constexpr (CH < n_chunks(MP)) {
+        f(std::integral_constant<int, CH>{});
+        for_chunks<MP, CH + 1>(f);
+    }
+}
+
+// Reduce-scatter of chunk CH: v holds the lane's partials of the chunk's n
+// columns; the two row swaps leave the 4-lane sums in q[q0 .. q0 + H2).
+template <int MP, int CH>
+__device__ __forceinline__ void scatter_chunk(const float* v, float (&q)[n_slots(MP)]) {
+    constexpr ChunkInfo c = chunk_info(MP, CH);
+    unsigned x[c.H1], y[c.H1];
+#pragma unroll
+    for (int j = 0; j < c.H1; ++j) {
+        x[j] = __builtin_bit_cast(unsigned, v[j]);
+        y[j] = (j + c.H1 < c.n) ? __builtin_bit_cast(unsigned, v[j + c.H1]) : 0u;
+    }
+    swap32_batch<c.H1>(x, y);
+    float h[c.H1];
+#pragma unroll
+    for (int j = 0; j < c.H1; ++j)
+        h[j] = __builtin_bit_cast(float, x[j]) + __builtin_bit_cast(float, y[j]);
+    unsigned x2[c.H2], y2[c.H2];
+#pragma unroll
+    for (int j = 0; j < c.H2; ++j) {
+        x2[j] = __builtin_bit_cast(unsigned, h[j]);
+        y2[j] = (j + c.H2 < c.H1) ? __builtin_bit_cast(unsigned, h[j + c.H2]) : 0u;
+    }
+    swap16_batch<c.H2>(x2, y2);
+#pragma unroll
+    for (int j = 0; j < c.H2; ++j)
+        q[c.q0 + j] = __builtin_bit_cast(float, x2[j]) + __builtin_bit_cast(float, y2[j]);
+}
+
+template <int MP>
+__device__ __forceinline__ void scatter_all(const float (&acc)[MP], float (&q)[n_slots(MP)]) {
+    __builtin_amdgcn_sched_barrier(0);
+    for_chunks<MP>([&](auto ch) {
+        constexpr int CH = decltype(ch)::value;
+        scatter_chunk<MP, CH>(acc + 16 * CH, q);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Team total of the lane's own column from the scattered wave partials q
+// (every wave of the team ends with the same value, summed in wave order).
+template <int MP>
+__device__ __forceinline__ float wide_total(float (&q)[n_slots(MP)], const Team& tm, int col,
+                                            float* red, int par) {
+    constexpr int Q = n_slots(MP);
+    group_allreduce<Q>(q, 16);
+    float tot = pick_lane<Q>(q, tm.lw & 15);
+    if (tm.multi) {
+        float* buf = red + par * (tm.W * MP);
+        if (col >= 0) buf[tm.wt * MP + col] = tot;
+        __syncthreads();
+        tot = 0.f;
+        if (col >= 0)
+            for (int w = 0; w < tm.W; ++w) tot += buf[w * MP + col];
+    }
+    return tot;
+}
+
+// Broadcast of the owners' values: v[k] = x of lane lane_of(k), as scalars.
+template <int MP, int K = 0>
+__device__ __forceinline__ void spread_owned(float x, float (&v)[MP]) {
+    if constexpr (K < MP) {
+        v[K] = lane_value<lane_of(MP, K)>(x);
+        spread_owned<MP, K + 1>(x, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exponentials of one row: e_k = 2^(c_k c2 + gam_k - sh), s = sum_k e_k.
+// sh is S unless `exact` or the sum leaves range; returns sh.
+template <int MP>
+__device__ __forceinline__ float row_exp(const float (&c)[MP], const float (&gam)[MP], float c2,
+                                         float S, bool exact, float (&e)[MP], float& s) {
+    if (!exact) {
+#pragma unroll
+        for (int k = 0; k < MP; ++k) e[k] = ex2(fmaf(c[k], c2, gam[k]) - S);
+        s = Tree<MP>::sum(e);
+        if (s >= kShiftLo && s <= kShiftHi) return S;
+    }
+    const float c2m = opaque(c2);
+#pragma unroll
+    for (int k = 0; k < MP; ++k) e[k] = fmaf(c[k], c2m, gam[k]);
+    const float sh = Tree<MP>::max(e);
+#pragma unroll
+    for (int k = 0; k < MP; ++k) e[k] = ex2(e[k] - sh);
+    s = Tree<MP>::sum(e);
+    return sh;
+}
+
+// s = sum_k e_k and, if GH, d = sum_k e_k gh_k for shift sh, without keeping
+// the exponentials.  Four partial sums shorten the dependency chains.
+template <int MP, bool GH>
+__device__ __forceinline__ void row_sums(const float (&c)[MP], const float (&gam)[MP],
+                                         const float (&gh)[MP], float c2, float sh, float& s,
+                                         float& d) {
+    float ps[4] = {0.f, 0.f, 0.f, 0.f}, pd[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const float e = ex2(fmaf(c[k], c2, gam[k]) - sh);
+        ps[k & 3] += e;
+        if (GH) pd[k & 3] = fmaf(e, gh[k], pd[k & 3]);
+    }
+    s = (ps[0] + ps[1]) + (ps[2] + ps[3]);
+    d = (pd[0] + pd[1]) + (pd[2] + pd[3]);
+}
+
+template <int MP, bool GH>
+__device__ __forceinline__ float row_stats(const float (&c)[MP], const float (&gam)[MP],
+                                           const float (&gh)[MP], float c2, float S, bool exact,
+                                           float& s, float& d) {
+    if (!exact) {
+        row_sums<MP, GH>(c, gam, gh, c2, S, s, d);
+        if (s >= kShiftLo && s <= kShiftHi) return S;
+    }
+    const float c2m = opaque(c2);
+    float mx[4] = {kNeg, kNeg, kNeg, kNeg};
+#pragma unroll
+    for (int k = 0; k < MP; ++k) mx[k & 3] = fmaxf(mx[k & 3], fmaf(c[k], c2m, gam[k]));
+    const float sh = fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3]));
+    row_sums<MP, GH>(c, gam, gh, opaque(c2), sh, s, d);
+    return sh;
+}
+
+// ---------------------------------------------------------------------------
+// Column state of a team: the potentials gam (registers of every lane for
+// narrow teams; wave-uniform scalars for wide ones, with the owner lane's
+// copy gd) and the per-column constants.
+template <int MP, bool WIDE>
+struct Cols;
+
+template <int MP>
+struct Cols<MP, false> {
+    float lb[MP];    // log2 b_k
+    float ib[MP];    // 1 / b_k
+    __device__ __forceinline__ void init(const Team&, int m, float lbd, float ibd, float (&gam)[MP]) {
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            gam[k] = (k < m) ? 0.f : kNeg;
+            lb[k] = (k == m - 1) ? lbd : 0.f;
+            ib[k] = (k == m - 1) ? ibd : 1.f;
+        }
+    }
+};
+
+template <int MP>
+struct Cols<MP, true> {
+    int col;      // column this lane owns after the reduce-scatter (-1: none)
+    bool live;    // col < m
+    float lbc;    // log2 b_col
+    float ibc;    // 1 / b_col
+    float gd;     // gamma_col
+    __device__ __forceinline__ void init(const Team& tm, int m, float lbd, float ibd, float (&gam)[MP]) {
+        col = owned_col<MP>(tm.lw);
+        live = col >= 0 && col < m;
+        lbc = (col == m - 1) ? lbd : 0.f;
+        ibc = (col == m - 1) ? ibd : 1.f;
+        gd = live ? 0.f : kNeg;
+        spread_owned<MP>(gd, gam);
+    }
+};
+
+// Stores the MP column potentials of a team (kNeg on padding) at dst:
+// history or LDS segment.
+template <int MP, bool WIDE>
+__device__ __forceinline__ void put_gamma(float* dst, const float (&gam)[MP],
+                                          const Cols<MP, WIDE>& cs, const Team& tm) {
+    if constexpr (WIDE) {
+        if (tm.wt == 0 && cs.col >= 0) dst[cs.col] = cs.gd;
+    } else {
+        if (tm.lt == 0) {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) dst[k] = gam[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward row half-step.  Keeps one row of exponentials: acc gets the lane's
+// column partials sum_i P_ik.  S: shifts in, row log-sum-exps out.
 template <int MP, int R>
-__device__ __forceinline__ void row_step(const float (&c)[R][MP], const float (&om)[R],
-                                         const float (&gam)[MP], float c2, float (&acc)[MP],
-                                         float (&Mo)[R], float (&so)[R]) {
+__device__ __forceinline__ void row_pass(const float (&c)[R][MP], const float (&om)[R],
+                                         const float (&gam)[MP], float c2, bool exact,
+                                         float (&acc)[MP], float (&S)[R]) {
 #pragma unroll
     for (int k = 0; k < MP; ++k) acc[k] = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        float z[MP];
-#pragma unroll
-        for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], c2, gam[k]);
-        const float M = Tree<MP>::max(z);
-#pragma unroll
-        for (int k = 0; k < MP; ++k) z[k] = ex2(z[k] - M);
-        const float s = Tree<MP>::sum(z);
+        float e[MP], s;
+        const float sh = row_exp<MP>(c[j], gam, c2, S[j], exact, e, s);
         const float w = om[j] * rcp(s);
 #pragma unroll
-        for (int k = 0; k < MP; ++k) acc[k] = fmaf(z[k], w, acc[k]);
-        Mo[j] = M;
-        so[j] = s;
+        for (int k = 0; k < MP; ++k) acc[k] = fmaf(e[k], w, acc[k]);
+        S[j] = sh + lg2(s);
     }
 }
 
-template <int MP>
-__device__ __forceinline__ void store_gamma(float* dst, const float (&gam)[MP], int m) {
+// Recompute variant (wide teams): row sums first, then the column partials
+// chunk by chunk, each chunk scattered as soon as it is complete.
+template <int MP, int R>
+__device__ __forceinline__ void row_pass_recomp(const float (&c)[R][MP], const float (&om)[R],
+                                                const float (&gam)[MP], float c2, bool exact,
+                                                float (&q)[n_slots(MP)], float (&S)[R]) {
+    float w[R], sh[R];
 #pragma unroll
-    for (int k = 0; k < MP; ++k)
-        if (k < m) dst[k] = gam[k];
+    for (int j = 0; j < R; ++j) {
+        float s, d;
+        sh[j] = row_stats<MP, false>(c[j], gam, gam, c2, S[j], exact, s, d);
+        w[j] = om[j] * rcp(s);
+        S[j] = sh[j] + lg2(s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const float c2p = opaque(c2);
+    for_chunks<MP>([&](auto ch) {
+        constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+        float v[ci.n];
+#pragma unroll
+        for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) {
+                const int k = ci.k0 + kk;
+                v[kk] = fmaf(ex2(fmaf(c[j][k], c2p, gam[k]) - sh[j]), w[j], v[kk]);
+            }
+        }
+        scatter_chunk<MP, decltype(ch)::value>(v, q);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Column half-step: gamma_k += log2 b_k - log2 sig_k.
+template <int MP>
+__device__ __forceinline__ void col_update(float (&acc)[MP], float (&gam)[MP],
+                                           const Cols<MP, false>& cs, int m, const Team& tm) {
+    group_allreduce<MP>(acc, tm.L);
+#pragma unroll
+    for (int k = 0; k < MP; ++k) gam[k] += cs.lb[k] - lg2(fmaxf(acc[k], kTiny));
+    (void)m;
+}
+
+template <int MP>
+__device__ __forceinline__ void col_update_wide(float (&q)[n_slots(MP)], float (&gam)[MP],
+                                                Cols<MP, true>& cs, const Team& tm, float* red,
+                                                int par) {
+    const float tot = wide_total<MP>(q, tm, cs.col, red, par);
+    if (cs.live) cs.gd += cs.lbc - lg2(tot);
+    spread_owned<MP>(cs.gd, gam);
+}
+
+// One forward Sinkhorn iteration of a team.
+template <int MP, int R, bool WIDE, bool RECOMP>
+__device__ __forceinline__ void fwd_iter(const float (&c)[R][MP], const float (&om)[R],
+                                         float (&gam)[MP], float c2, bool exact, float (&S)[R],
+                                         Cols<MP, WIDE>& cs, int m, const Team& tm, float* red,
+                                         int par) {
+    if constexpr (!WIDE) {
+        float acc[MP];
+        row_pass<MP, R>(c, om, gam, c2, exact, acc, S);
+        col_update<MP>(acc, gam, cs, m, tm);
+    } else {
+        float q[n_slots(MP)];
+        if constexpr (RECOMP) {
+            row_pass_recomp<MP, R>(c, om, gam, c2, exact, q, S);
+        } else {
+            float acc[MP];
+            row_pass<MP, R>(c, om, gam, c2, exact, acc, S);
+            scatter_all<MP>(acc, q);
+        }
+        col_update_wide<MP>(q, gam, cs, tm, red, par);
+    }
 }
 
 template <int MP, int R>
@@ -158,15 +451,16 @@ __device__ __forceinline__ void load_costs(const float* C, int64_t u, bool activ
         const bool valid = active && i < I;
         om[j] = valid ? 1.f : 0.f;
         const float* src = C + (u * I + i) * (int64_t)m;
+        // padded columns repeat the last cost; their potential kNeg zeroes them
 #pragma unroll
-        for (int k = 0; k < MP; ++k) c[j][k] = (valid && k < m) ? src[k] : 0.f;
+        for (int k = 0; k < MP; ++k) c[j][k] = valid ? src[k < m ? k : m - 1] : 0.f;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Forward for the teams of one block: team q of the block owns consumer
 // u_first + q.
-template <int MP, int R>
+template <int MP, int R, bool WIDE, bool RECOMP>
 __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int64_t u = u_first + tm.team;
@@ -178,75 +472,198 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
     float c[R][MP], om[R];
     load_costs<MP, R>(a.C, u, active, tm, I, m, c, om);
 
-    float gam[MP], lb[MP];
-    const float lbd = lg2((float)(I - m + 1));
-#pragma unroll
-    for (int k = 0; k < MP; ++k) {
-        gam[k] = (k < m) ? 0.f : kNeg;
-        lb[k] = (k == m - 1) ? lbd : 0.f;
-    }
+    float gam[MP];
+    Cols<MP, WIDE> cs;
+    cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gam);
     float* hist = (a.hist != nullptr && active) ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
-    if (hist && tm.lt == 0) store_gamma<MP>(hist, gam, m);
+    if (hist) put_gamma<MP, WIDE>(hist, gam, cs, tm);
 
-    float Ml[R], sl[R], acc[MP];
+    float S[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) S[j] = 0.f;
     for (int t = 1; t <= a.T; ++t) {
-        row_step<MP, R>(c, om, gam, a.c2, acc, Ml, sl);
-        column_step<MP>(acc, gam, lb, m, tm, red, t & 1);
-        if (hist && tm.lt == 0) {
+        fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, a.c2, t == 1, S, cs, m, tm, red, t & 1);
+        if (hist) {
             if (t % a.K == 0)
-                store_gamma<MP>(hist + (int64_t)(t / a.K) * a.hs, gam, m);
+                put_gamma<MP, WIDE>(hist + (int64_t)(t / a.K) * a.hs, gam, cs, tm);
             else if (t == a.T)
-                store_gamma<MP>(hist + (int64_t)(a.nck - 1) * a.hs, gam, m);
+                put_gamma<MP, WIDE>(hist + (int64_t)(a.nck - 1) * a.hs, gam, cs, tm);
         }
     }
 
+    const int mo = opaque_u(m);
     float ek[MP];
 #pragma unroll
-    for (int k = 0; k < MP; ++k) ek[k] = (k < m - 1) ? a.e[k] : 0.f;
+    for (int k = 0; k < MP; ++k) ek[k] = (k < mo - 1) ? a.e[k] : 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int i = tm.lt + j * tm.L;
         if (!(active && i < I)) continue;
-        const float phi = -(Ml[j] + lg2(sl[j]));
+        const float phi = -S[j];
         const int64_t row = u * I + i;
-        float x[MP];
         float yy = 0.f;
+        if (a.X && a.x_bf16) {
+            uint16_t* dst = (uint16_t*)a.X + row * m;
 #pragma unroll
-        for (int k = 0; k < MP; ++k) {
-            x[k] = ex2(fmaf(c[j][k], a.c2, gam[k]) + phi);
-            yy = fmaf(ek[k], x[k], yy);
+            for (int k = 0; k < MP; ++k) {
+                const float x = ex2(fmaf(c[j][k], a.c2, gam[k]) + phi);
+                yy = fmaf(ek[k], x, yy);
+                if (k < mo) dst[k] = to_bf16(x);
+            }
+        } else if (a.X) {
+            float* dst = (float*)a.X + row * m;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                const float x = ex2(fmaf(c[j][k], a.c2, gam[k]) + phi);
+                yy = fmaf(ek[k], x, yy);
+                if (k < mo) dst[k] = x;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k)
+                yy = fmaf(ek[k], ex2(fmaf(c[j][k], a.c2, gam[k]) + phi), yy);
         }
         if (a.y) a.y[row] = a.r[row] * yy;
-        if (a.X) {
-            if (a.x_bf16) {
-                uint16_t* dst = (uint16_t*)a.X + row * m;
-#pragma unroll
-                for (int k = 0; k < MP; ++k)
-                    if (k < m) dst[k] = to_bf16(x[k]);
-            } else {
-                float* dst = (float*)a.X + row * m;
-#pragma unroll
-                for (int k = 0; k < MP; ++k)
-                    if (k < m) dst[k] = x[k];
-            }
-        }
         if (a.pot) a.pot[u * (int64_t)(I + m) + i] = phi * a.eps_ln2;
     }
     if (a.pot && active && tm.lt == 0) {
 #pragma unroll
         for (int k = 0; k < MP; ++k)
-            if (k < m) a.pot[u * (int64_t)(I + m) + I + k] = gam[k] * a.eps_ln2;
+            if (k < mo) a.pot[u * (int64_t)(I + m) + I + k] = gam[k] * a.eps_ln2;
     }
 }
 
-template <int MP, int R, int LB>
-__global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
-    extern __shared__ float smem[];
-    fwd_body<MP, R>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+// ---------------------------------------------------------------------------
+// Backward pieces.  Reverse of iteration t for the lane's rows: gp = gamma^{t-1},
+// gh_k = gbar_k / sig^t_k; cb += P (gh + fbar); the lane's share of
+// sum_i P_ik fbar_i goes to acc (or, recompute variant, to the scattered q).
+template <int MP, int R>
+__device__ __forceinline__ void rev_pass(const float (&c)[R][MP], const float (&om)[R],
+                                         const float (&gp)[MP], const float (&gh)[MP], float c2,
+                                         const float (&fb0)[R], bool first, float (&cb)[R][MP],
+                                         float (&acc)[MP], float (&S)[R]) {
+#pragma unroll
+    for (int k = 0; k < MP; ++k) acc[k] = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float e[MP], s;
+        const float sh = row_exp<MP>(c[j], gp, c2, S[j], false, e, s);
+        float pd[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MP; ++k) pd[k & 3] = fmaf(e[k], gh[k], pd[k & 3]);
+        const float d = (pd[0] + pd[1]) + (pd[2] + pd[3]);
+        const float w = om[j] * rcp(s);
+        const float fb = (first ? fb0[j] : 0.f) - w * d;
+        const float aa = w * fb;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            cb[j][k] = fmaf(e[k], fmaf(w, gh[k], aa), cb[j][k]);
+            acc[k] = fmaf(e[k], aa, acc[k]);
+        }
+        S[j] = sh + lg2(s);
+    }
 }
 
-// ---------------------------------------------------------------------------
 template <int MP, int R>
+__device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const float (&om)[R],
+                                                const float (&gp)[MP], const float (&gh)[MP],
+                                                float c2, const float (&fb0)[R], bool first,
+                                                float (&cb)[R][MP], float (&q)[n_slots(MP)],
+                                                float (&S)[R]) {
+    float sh[R], w[R], aa[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float s, d;
+        sh[j] = row_stats<MP, true>(c[j], gp, gh, c2, S[j], false, s, d);
+        w[j] = om[j] * rcp(s);
+        const float fb = (first ? fb0[j] : 0.f) - w[j] * d;
+        aa[j] = w[j] * fb;
+        S[j] = sh[j] + lg2(s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const float c2p = opaque(c2);
+    for_chunks<MP>([&](auto ch) {
+        constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+        float v[ci.n];
+#pragma unroll
+        for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) {
+                const int k = ci.k0 + kk;
+                const float e = ex2(fmaf(c[j][k], c2p, gp[k]) - sh[j]);
+                cb[j][k] = fmaf(e, fmaf(w[j], gh[k], aa[j]), cb[j][k]);
+                v[kk] = fmaf(e, aa[j], v[kk]);
+            }
+        }
+        scatter_chunk<MP, decltype(ch)::value>(v, q);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Start of the reverse sweep (t = T): X = P^T diag(rho), rho_k = b_k / sig^T_k,
+// and the adjoints of X = exp((f + g - c)/eps): cb = -G X / eps,
+// fb0 = (G X) 1 / eps, acc (or q) = the lane's share of (G X)^T 1 / eps;
+// also dr = gF e.X / Imp.  Rows are processed chunk by chunk with the
+// exponentials recomputed, so no row of them is kept.
+template <int MP, int R, bool WIDE>
+__device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][MP],
+                                         const float (&om)[R], const float (&gp)[MP],
+                                         const float (&rho)[MP], const float (&rg)[R],
+                                         float (&fb0)[R], float (&cb)[R][MP],
+                                         float (&acc)[WIDE ? 1 : MP], float (&q)[n_slots(MP)],
+                                         float (&S)[R], int64_t u, bool active, const Team& tm) {
+    const int m = opaque_u(a.m);
+    float ek[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) ek[k] = (k < m - 1) ? a.e[k] : 0.f;
+    float sh[R], w[R], xe[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float s, d;
+        sh[j] = row_stats<MP, false>(c[j], gp, gp, a.c2, 0.f, true, s, d);
+        w[j] = om[j] * rcp(s) * a.inv_eps;
+        S[j] = sh[j] + lg2(s);
+        fb0[j] = 0.f;
+        xe[j] = 0.f;
+    }
+    const float c2p = opaque(a.c2);
+    for_chunks<MP>([&](auto ch) {
+        constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+        float v[ci.n];
+#pragma unroll
+        for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) {
+                const int k = ci.k0 + kk;
+                // xs = x / eps, gx = G x / eps
+                const float xs = ex2(fmaf(c[j][k], c2p, gp[k]) - sh[j]) * w[j] * rho[k];
+                const float gx = rg[j] * ek[k] * xs;
+                cb[j][k] = -gx;
+                fb0[j] += gx;
+                v[kk] += gx;
+                xe[j] = fmaf(ek[k], xs, xe[j]);
+            }
+        }
+        if constexpr (WIDE) {
+            scatter_chunk<MP, decltype(ch)::value>(v, q);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) acc[ci.k0 + kk] = v[kk];
+        }
+    });
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        if (a.dr && active && i < a.I)
+            a.dr[u * a.I + i] = (float)(a.gF / a.imp[i]) * (xe[j] / a.inv_eps);
+    }
+}
+
+template <int MP, int R, bool WIDE, bool RECOMP>
 __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int teams = blockDim.x / a.L;
@@ -266,22 +683,21 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
         const int i = tm.lt + j * tm.L;
         rg[j] = (active && i < I) ? (float)(a.gF * (double)a.r[u * I + i] / a.imp[i]) : 0.f;
     }
-    float lb[MP];
-    const float lbd = lg2((float)(I - m + 1));
-    const float invbd = 1.0f / (float)(I - m + 1);
-#pragma unroll
-    for (int k = 0; k < MP; ++k) lb[k] = (k == m - 1) ? lbd : 0.f;
+    float gam[MP];   // recomputed potentials (K > 1 segments)
+    Cols<MP, WIDE> cs;
+    cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gam);
 
     const float* hist = active ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
-    float cb[R][MP], fb0[R], gbar[MP], acc[MP], Ml[R], sl[R];
+    float cb[R][MP], fb0[R], Sb[R], Sf[R];
+    float gbar[WIDE ? 1 : MP];   // narrow: every column; wide: the owned column
+#pragma unroll
+    for (int k = 0; k < (WIDE ? 1 : MP); ++k) gbar[k] = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         fb0[j] = 0.f;
-#pragma unroll
-        for (int k = 0; k < MP; ++k) cb[j][k] = 0.f;
+        Sb[j] = 0.f;
+        Sf[j] = 0.f;
     }
-#pragma unroll
-    for (int k = 0; k < MP; ++k) gbar[k] = 0.f;
 
     int par = 0;
     const int nblk = (a.K == 1) ? (a.T + BL - 1) / BL : (a.nck - 1);
@@ -292,111 +708,90 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
         __syncthreads();  // the previous block's reads of seg are complete
         if (a.K == 1) {
             for (int idx = tm.lt; idx < (n + 1) * MP; idx += tm.L) {
-                const int q = idx / MP, k = idx - q * MP;
-                seg[idx] = (active && k < m) ? hist[(int64_t)(t0 + q) * a.hs + k] : kNeg;
+                const int qq = idx / MP, k = idx - qq * MP;
+                seg[idx] = active ? hist[(int64_t)(t0 + qq) * a.hs + k] : 0.f;
             }
         } else {
-            float gam[MP];
+            // rebuild gamma^{t0} .. gamma^{t1} from the checkpoint
+            if constexpr (WIDE) {
+                cs.gd = (active && cs.col >= 0) ? hist[(int64_t)s * a.hs + cs.col] : kNeg;
+                spread_owned<MP>(cs.gd, gam);
+            } else {
 #pragma unroll
-            for (int k = 0; k < MP; ++k)
-                gam[k] = (active && k < m) ? hist[(int64_t)s * a.hs + k] : kNeg;
-            if (tm.lt == 0) {
-#pragma unroll
-                for (int k = 0; k < MP; ++k) seg[k] = gam[k];
+                for (int k = 0; k < MP; ++k) gam[k] = active ? hist[(int64_t)s * a.hs + k] : kNeg;
             }
-            for (int q = 1; q <= n; ++q) {
-                row_step<MP, R>(c, om, gam, a.c2, acc, Ml, sl);
-                column_step<MP>(acc, gam, lb, m, tm, red, par);
+            put_gamma<MP, WIDE>(seg, gam, cs, tm);
+            for (int qq = 1; qq <= n; ++qq) {
+                fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, a.c2, qq == 1, Sf, cs, m, tm, red, par);
                 par ^= 1;
-                if (tm.lt == 0) {
-#pragma unroll
-                    for (int k = 0; k < MP; ++k) seg[q * MP + k] = gam[k];
-                }
+                put_gamma<MP, WIDE>(seg + qq * MP, gam, cs, tm);
             }
         }
         __syncthreads();
 
-        for (int q = n; q >= 1; --q) {
-            const int t = t0 + q;
-            float gp[MP];
+        for (int qq = n; qq >= 1; --qq) {
+            const int t = t0 + qq;
+            const float* sq = seg + qq * MP;        // gamma^t
+            const float* sp = seg + (qq - 1) * MP;  // gamma^{t-1}
+            float gp[MP], gh[MP];
+            if constexpr (WIDE) {
+                spread_owned<MP>((cs.col >= 0) ? sp[cs.col] : kNeg, gp);
+            } else {
 #pragma unroll
-            for (int k = 0; k < MP; ++k) gp[k] = seg[(q - 1) * MP + k];
+                for (int k = 0; k < MP; ++k) gp[k] = sp[k];
+            }
 
             if (t == a.T) {
-                // X = P^T * b / sig^T and the adjoints of X = exp((f+g-c)/eps).
+                float rho[MP];
 #pragma unroll
-                for (int k = 0; k < MP; ++k) acc[k] = 0.f;
+                for (int k = 0; k < MP; ++k) rho[k] = ex2(sq[k] - gp[k]);   // 1 on padding
+                float acc[WIDE ? 1 : MP];
+                float q[n_slots(MP)];
+                rev_init<MP, R, WIDE>(a, c, om, gp, rho, rg, fb0, cb, acc, q, Sb, u, active, tm);
+                if constexpr (WIDE) {
+                    gbar[0] = wide_total<MP>(q, tm, cs.col, red, par);
+                } else {
+                    group_allreduce<MP>(acc, tm.L);
 #pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    float z[MP];
-#pragma unroll
-                    for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], a.c2, gp[k]);
-                    const float M = Tree<MP>::max(z);
-#pragma unroll
-                    for (int k = 0; k < MP; ++k) z[k] = ex2(z[k] - M);
-                    const float w = om[j] * rcp(Tree<MP>::sum(z));
-                    float gsum = 0.f, xe = 0.f;
-#pragma unroll
-                    for (int k = 0; k < MP; ++k) {
-                        const float rho = (k < m) ? ex2(seg[q * MP + k] - gp[k]) : 0.f;
-                        const float ekk = (k < m - 1) ? a.e[k] : 0.f;
-                        const float x = z[k] * w * rho;
-                        const float gx = rg[j] * ekk * x * a.inv_eps;
-                        cb[j][k] = -gx;
-                        gsum += gx;
-                        acc[k] += gx;
-                        xe = fmaf(ekk, x, xe);
-                    }
-                    fb0[j] = gsum;
-                    const int i = tm.lt + j * tm.L;
-                    if (a.dr && active && i < I)
-                        a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * xe;
+                    for (int k = 0; k < MP; ++k) gbar[k] = acc[k];
                 }
-                team_sum<MP>(acc, tm, red, par);
                 par ^= 1;
+            }
+
+            // gh_k = gbar_k / sig^t_k
+            if constexpr (WIDE) {
+                const float ghd = cs.live ? gbar[0] * ex2(sq[cs.col] - sp[cs.col]) * cs.ibc : 0.f;
+                spread_owned<MP>(ghd, gh);
+            } else {
 #pragma unroll
-                for (int k = 0; k < MP; ++k) gbar[k] = acc[k];
+                for (int k = 0; k < MP; ++k) gh[k] = gbar[k] * ex2(sq[k] - gp[k]) * cs.ib[k];
             }
 
             // reverse of iteration t
-            float gh[MP];
-#pragma unroll
-            for (int k = 0; k < MP; ++k) {
-                const float ib = (k == m - 1) ? invbd : 1.0f;
-                gh[k] = (k < m) ? gbar[k] * ex2(seg[q * MP + k] - gp[k]) * ib : 0.f;
-            }
-#pragma unroll
-            for (int k = 0; k < MP; ++k) acc[k] = 0.f;
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                float z[MP], zg[MP];
-#pragma unroll
-                for (int k = 0; k < MP; ++k) z[k] = fmaf(c[j][k], a.c2, gp[k]);
-                const float M = Tree<MP>::max(z);
-#pragma unroll
-                for (int k = 0; k < MP; ++k) {
-                    z[k] = ex2(z[k] - M);
-                    zg[k] = z[k] * gh[k];
+            if constexpr (WIDE) {
+                float q[n_slots(MP)];
+                if constexpr (RECOMP) {
+                    rev_pass_recomp<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, q, Sb);
+                } else {
+                    float acc[MP];
+                    rev_pass<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, acc, Sb);
+                    scatter_all<MP>(acc, q);
                 }
-                const float w = om[j] * rcp(Tree<MP>::sum(z));
-                const float d = Tree<MP>::sum(zg);
-                const float fb = (t == a.T ? fb0[j] : 0.f) - w * d;
-                const float aa = w * fb;
+                gbar[0] = -wide_total<MP>(q, tm, cs.col, red, par);
+            } else {
+                float acc[MP];
+                rev_pass<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, acc, Sb);
+                group_allreduce<MP>(acc, tm.L);
 #pragma unroll
-                for (int k = 0; k < MP; ++k) {
-                    cb[j][k] = fmaf(z[k], fmaf(w, gh[k], aa), cb[j][k]);
-                    acc[k] = fmaf(z[k], aa, acc[k]);
-                }
+                for (int k = 0; k < MP; ++k) gbar[k] = -acc[k];
             }
-            team_sum<MP>(acc, tm, red, par);
             par ^= 1;
-#pragma unroll
-            for (int k = 0; k < MP; ++k) gbar[k] = -acc[k];
         }
     }
 
     // epilogue: write gF * dF/dC, or apply the ascent step to C in place
     if (!active) return;
+    const int mo = opaque_u(m);
     float bc1 = 1.f, bc2 = 1.f;
     if (a.Cw && a.rule == 0) {
         const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
@@ -410,7 +805,7 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
         const int64_t base = (u * I + i) * (int64_t)m;
 #pragma unroll
         for (int k = 0; k < MP; ++k) {
-            if (k >= m) continue;
+            if (k >= mo) continue;
             const float g = cb[j][k];
             if (a.dC) a.dC[base + k] = g;
             if (a.Cw) {
@@ -429,123 +824,180 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     }
 }
 
-template <int MP, int R, int LB>
+// ---------------------------------------------------------------------------
+// Per-lane registers available at launch bound LB (512 per SIMD lane shared
+// by LB / 256 waves, at most 256 architectural VGPRs), minus a reserve for
+// addresses and temporaries.
+constexpr int reg_budget(int LB) { return (131072 / LB < 256 ? 131072 / LB : 256) - 32; }
+template <int R, int LB, bool WIDE>
+constexpr bool recomp_fwd() { return WIDE && (R * FR_MP + 2 * FR_MP > reg_budget(LB)); }
+template <int R, int LB, bool WIDE>
+constexpr bool recomp_bwd() { return WIDE && (2 * R * FR_MP + 2 * FR_MP > reg_budget(LB)); }
+
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
+    extern __shared__ float smem[];
+    fwd_body<MP, R, WIDE, recomp_fwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
+                                                     smem);
+}
+
+template <int MP, int R, int LB, bool WIDE>
 __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
     extern __shared__ float smem[];
-    bwd_body<MP, R>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+    bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
+                                                     smem);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent batched kernels: every block repeatedly takes the next work item
 // (instance, first consumer) from a global counter and runs the same team
 // body on it, until the list is exhausted.  Items are ordered longest first.
-template <int MP, int R, int LB>
-__global__ __launch_bounds__(LB) void k_bfwd(const FwdArgs* __restrict__ descs,
-                                             const BatchItem* __restrict__ items, int n_items,
-                                             unsigned* counter) {
+template <int MP, int R, bool WIDE>
+__global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
+                                              const BatchItem* __restrict__ items, int n_items,
+                                              unsigned* counter) {
     extern __shared__ float smem[];
     __shared__ int s_item;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= n_items) break;
         const BatchItem bi = items[it];
         const FwdArgs a = descs[bi.inst];
-        fwd_body<MP, R>(a, bi.u0, smem);
+        fwd_body<MP, R, WIDE, recomp_fwd<R, 256, WIDE>()>(a, bi.u0, smem);
     }
 }
 
-template <int MP, int R, int LB>
-__global__ __launch_bounds__(LB) void k_bbwd(const BwdArgs* __restrict__ descs,
-                                             const BatchItem* __restrict__ items, int n_items,
-                                             unsigned* counter) {
+template <int MP, int R, bool WIDE>
+__global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
+                                              const BatchItem* __restrict__ items, int n_items,
+                                              unsigned* counter) {
     extern __shared__ float smem[];
     __shared__ int s_item;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= n_items) break;
         const BatchItem bi = items[it];
         const BwdArgs a = descs[bi.inst];
-        bwd_body<MP, R>(a, bi.u0, smem);
+        bwd_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
     }
 }
 
-template <int MP, int R, int LB>
+template <int MP, int R, bool WIDE>
 void launch_bfwd(const FwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bfwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+    hipLaunchKernelGGL((k_bfwd<MP, R, WIDE>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
 }
-template <int MP, int R, int LB>
+template <int MP, int R, bool WIDE>
 void launch_bbwd(const BwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bbwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+    hipLaunchKernelGGL((k_bbwd<MP, R, WIDE>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
 }
-template <int MP, int R, int LB>
+template <int MP, int R, bool WIDE>
 int occupancy_bfwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, LB>, block, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, WIDE>, block, lds) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
-template <int MP, int R, int LB>
+template <int MP, int R, bool WIDE>
 int occupancy_bbwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, LB>, block, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, WIDE>, block, lds) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <int MP, int R, int LB>
+template <int MP, int R, int LB, bool WIDE>
 void launch_fwd(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_fwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
-template <int MP, int R, int LB>
+template <int MP, int R, int LB, bool WIDE>
 void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bwd<MP, R, LB>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_bwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
 
-template <int R, int LB>
+template <int R, int LB, bool WIDE>
 constexpr FusedEntry entry() {
-    return FusedEntry{FR_MP,
-                      R,
-                      LB,
-                      &launch_fwd<FR_MP, R, LB>,
-                      &launch_bwd<FR_MP, R, LB>,
-                      &launch_bfwd<FR_MP, R, LB>,
-                      &launch_bbwd<FR_MP, R, LB>,
-                      &occupancy_bfwd<FR_MP, R, LB>,
-                      &occupancy_bbwd<FR_MP, R, LB>};
+    if constexpr (LB == 256) {
+        return FusedEntry{FR_MP,
+                          R,
+                          LB,
+                          WIDE,
+                          recomp_fwd<R, LB, WIDE>(),
+                          recomp_bwd<R, LB, WIDE>(),
+                          &launch_fwd<FR_MP, R, LB, WIDE>,
+                          &launch_bwd<FR_MP, R, LB, WIDE>,
+                          &launch_bfwd<FR_MP, R, WIDE>,
+                          &launch_bbwd<FR_MP, R, WIDE>,
+                          &occupancy_bfwd<FR_MP, R, WIDE>,
+                          &occupancy_bbwd<FR_MP, R, WIDE>};
+    } else {
+        return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
+                          &launch_fwd<FR_MP, R, LB, WIDE>,
+                          &launch_bwd<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr};
+    }
 }
 
-// Rows per lane instantiated for this column class: the register-resident
-// plan share R * MP stays within 128 floats per lane.
-#define FR_ROWS_OK(R) ((R) * FR_MP <= 128)
+// Rows per lane instantiated for this column class.  Narrow teams (several
+// per wave) keep R * MP <= 128 costs per lane; wave-wide teams up to 256 at
+// launch bounds 256 and 512 and up to 128 at launch bound 1024.
+#define FR_NARROW_OK(R) ((R) * FR_MP <= 128)
+#define FR_WIDE_OK(R) ((R) * FR_MP <= 256)
+#define FR_BIG_OK(R) ((R) * FR_MP <= 128)
 
 const FusedEntry kEntries[] = {
-    entry<1, 256>(),
-#if FR_ROWS_OK(2)
-    entry<2, 256>(),
+    entry<1, 256, false>(),
+#if FR_NARROW_OK(2)
+    entry<2, 256, false>(),
 #endif
-#if FR_ROWS_OK(3)
-    entry<3, 256>(),
+#if FR_NARROW_OK(3)
+    entry<3, 256, false>(),
 #endif
-#if FR_ROWS_OK(4)
-    entry<4, 256>(),
+#if FR_NARROW_OK(4)
+    entry<4, 256, false>(),
 #endif
-#if FR_ROWS_OK(6)
-    entry<6, 256>(),
+#if FR_NARROW_OK(6)
+    entry<6, 256, false>(),
 #endif
-#if FR_ROWS_OK(8)
-    entry<8, 256>(),
+#if FR_NARROW_OK(8)
+    entry<8, 256, false>(),
 #endif
-    entry<1, 1024>(),
-#if FR_ROWS_OK(2)
-    entry<2, 1024>(),
+    entry<1, 256, true>(),
+    entry<2, 256, true>(),
+#if FR_WIDE_OK(3)
+    entry<3, 256, true>(),
+#endif
+#if FR_WIDE_OK(4)
+    entry<4, 256, true>(),
+#endif
+#if FR_WIDE_OK(6)
+    entry<6, 256, true>(),
+#endif
+#if FR_WIDE_OK(8)
+    entry<8, 256, true>(),
+#endif
+    entry<1, 512, true>(),
+    entry<2, 512, true>(),
+#if FR_WIDE_OK(3)
+    entry<3, 512, true>(),
+#endif
+#if FR_WIDE_OK(4)
+    entry<4, 512, true>(),
+#endif
+    entry<1, 1024, true>(),
+#if FR_BIG_OK(2)
+    entry<2, 1024, true>(),
+#endif
+#if FR_BIG_OK(4)
+    entry<4, 1024, true>(),
 #endif
 };
 

@@ -71,9 +71,12 @@ typedef int (*Occupancy)(int block, size_t lds);
 
 struct FusedEntry {
     int mp, rows, lb;   // padded columns, rows per lane, launch bound (max block)
+    bool wide;          // teams of whole waves (L >= 64); else L < 64
+    bool recomp_f;      // forward recomputes each row's exponentials (register budget)
+    bool recomp_b;      // backward likewise
     FwdLaunch fwd;
     BwdLaunch bwd;
-    BFwdLaunch bfwd;    // persistent batched forms
+    BFwdLaunch bfwd;    // persistent batched forms (launch bound 256 only)
     BBwdLaunch bbwd;
     Occupancy occ_bfwd;
     Occupancy occ_bbwd;

@@ -157,7 +157,7 @@ def test_autotune_picks_a_valid_shape_and_keeps_parity(fr):
     inst = W.config("C1")
     prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
     L, R = ctx.autotune(prob)
-    assert ctx.get_launch(inst.I, inst.m) == (L, R) and L * R >= inst.I
+    assert ctx.get_launch(inst.U, inst.I, inst.m) == (L, R) and L * R >= inst.I
     Lb, Rb = ctx.autotune(prob, batched=True)
     assert Lb <= 256 and Lb * Rb >= inst.I
     res = fr.solve(ctx, prob, 5, float(inst.lr))

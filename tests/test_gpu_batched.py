@@ -98,4 +98,6 @@ def test_batched_ignores_team_widths_that_do_not_tile_its_blocks(fr):
     b = fr.solve_batched(ctx, [p], 2, 0.003)
     one = fr.solve(ctx, p, 2, 0.003)
     Fb, Fs = b[0]["F_hist"].cpu().numpy(), one["F_hist"].cpu().numpy()
-    assert np.all(np.isfinite(Fb)) and np.max(np.abs(Fb / Fs - 1)) <= 1e-7
+    # different launch shapes sum in different orders; Adam's first steps
+    # turn rounding-level gradient differences into lr-sized cost changes
+    assert np.all(np.isfinite(Fb)) and np.max(np.abs(Fb / Fs - 1)) <= F_REL
