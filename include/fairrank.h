@@ -121,6 +121,25 @@ fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
 fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,
                  double* imp, double* F, void* ws, size_t ws_bytes, void* stream);
 
+/* Evaluation metrics of a plan X [U][I][m] (x_dtype), from the list of
+ * evaluation metrics in Section 4.1.  With W_uj = sum_{k<m-1} e_k x_ujk and
+ * E_ij = sum_u r_ui W_uj (the impact item i would get with item j's
+ * allocation; E_ii is Eq. Imp):
+ *   out[0] user utility        = sum_i E_ii / U
+ *   out[1] mean max envy       = mean_i (max_j E_ij - E_ii)
+ *   out[2] items better off    = fraction of i with E_ii > 1.1 Imp_i^unif
+ *   out[3] items worse off     = fraction of i with E_ii < 0.9 Imp_i^unif
+ * where Imp_i^unif = (sum_u r_ui)(sum_{k<m-1} e_k) / I is the impact under the
+ * uniform ranking policy.  out: 4 doubles (device).  Optional (device, NULL =
+ * not written): envy [I] (max_j E_ij - E_ii) and imp [I] (E_ii).  W and E are
+ * FP64 (E on FP64 matrix cores; E is reduced tile by tile and never stored);
+ * the better / worse decisions are taken in FP64.  Asynchronous on the stream.
+ * Workspace from fr_workspace_bytes_metrics (independent of the solver's). */
+fr_status fr_workspace_bytes_metrics(const fr_problem* prob, size_t* out);
+fr_status fr_metrics(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,
+                     double* out, double* envy, double* imp, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* --------------------------------------------------------------- backward */
 /* Section 3 ("chain rule"): reverse mode through the T unrolled Sinkhorn
  * iterations.  Given C and the impacts imp [I] of X(C) (from fr_step), writes

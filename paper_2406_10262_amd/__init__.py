@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "load", "library_path", "FairRankError", "Context", "Problem", "step", "nsw",
-    "backward", "solve", "solve_plain", "solve_batched", "SinkhornNSW", "sinkhorn_nsw",
+    "backward", "solve", "solve_plain", "solve_batched", "SinkhornNSW", "sinkhorn_nsw", "metrics",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -92,10 +92,12 @@ def load():
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.fr_workspace_bytes_metrics.argtypes = [PP, ctypes.POINTER(SZ)]
+    lib.fr_metrics.argtypes = [P, PP, P, ctypes.c_int, P, P, P, P, SZ, P]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
-                 "fr_set_launch", "fr_get_launch"):
+                 "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -262,6 +264,37 @@ def nsw(ctx: Context, prob: Problem, X: torch.Tensor, sync: bool = True):
     if sync:
         _check(load().fr_sync_status(ctx.handle, _ptr(ws), _stream(X.device)), "fr_nsw (device)")
     return imp, F
+
+
+METRIC_NAMES = ("user_utility", "mean_max_envy", "items_better", "items_worse")
+
+
+def metrics(ctx: Context, prob: Problem, X: torch.Tensor, per_item: bool = False,
+            sync: bool = True):
+    """fr_metrics: user utility, mean max envy and the fractions of items better
+    / worse off than under the uniform policy (Section 4.1) of a plan X
+    [U, I, m] (float32 or bfloat16).  Returns the four values as a float64
+    device tensor (and, with per_item, the per-item envy and impacts)."""
+    U, I, m = prob.U, prob.I, prob.m
+    if tuple(X.shape) != (U, I, m) or not X.is_contiguous():
+        raise ValueError("X must be contiguous with shape (U, I, m)")
+    if X.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("X must be float32 or bfloat16")
+    p = prob.c()
+    nb = ctypes.c_size_t()
+    _check(load().fr_workspace_bytes_metrics(ctypes.byref(p), ctypes.byref(nb)),
+           "fr_workspace_bytes_metrics")
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=X.device)
+    out = torch.empty(4, dtype=torch.float64, device=X.device)
+    envy = torch.empty(I, dtype=torch.float64, device=X.device) if per_item else None
+    imp = torch.empty(I, dtype=torch.float64, device=X.device) if per_item else None
+    _check(load().fr_metrics(ctx.handle, ctypes.byref(p), _ptr(X),
+                             FR_BF16 if X.dtype == torch.bfloat16 else FR_F32, _ptr(out),
+                             _ptr(envy), _ptr(imp), _ptr(ws), ws.numel(), _stream(X.device)),
+           "fr_metrics")
+    if sync:
+        torch.cuda.synchronize(X.device)
+    return (out, envy, imp) if per_item else out
 
 
 def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF: float = 1.0,

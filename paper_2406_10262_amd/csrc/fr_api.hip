@@ -649,6 +649,70 @@ fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_
     return FR_OK;
 }
 
+// ---------------------------------------------------------------- metrics
+struct MetricsLayout {
+    size_t hdr, W, partial, rsum, pmax, diag, total;
+    int nchunk, tiles;
+};
+
+MetricsLayout metrics_layout(const fr_problem* p) {
+    MetricsLayout L;
+    const int64_t U = p->n_users;
+    const int I = p->n_items;
+    L.nchunk = impact_chunks(U, I);
+    L.tiles = metrics_tiles(I);
+    size_t off = 0;
+    L.hdr = off;
+    off += align_up(sizeof(WsHeader));
+    L.W = off;
+    off += align_up(sizeof(double) * (size_t)U * I);
+    L.partial = off;
+    off += align_up(sizeof(double) * (size_t)L.nchunk * I);
+    L.rsum = off;
+    off += align_up(sizeof(double) * I);
+    L.pmax = off;
+    off += align_up(sizeof(double) * (size_t)I * L.tiles);
+    L.diag = off;
+    off += align_up(sizeof(double) * I);
+    L.total = off;
+    return L;
+}
+
+fr_status fr_workspace_bytes_metrics(const fr_problem* prob, size_t* out) {
+    if (!out) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    *out = metrics_layout(prob).total;
+    return FR_OK;
+}
+
+fr_status fr_metrics(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,
+                     double* out, double* envy, double* imp, void* ws, size_t ws_bytes,
+                     void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!X || !out || !ws) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    const MetricsLayout Lw = metrics_layout(prob);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    MetricsBufs b;
+    b.hdr = (WsHeader*)(w + Lw.hdr);
+    b.W = (double*)(w + Lw.W);
+    b.partial = (double*)(w + Lw.partial);
+    b.nchunk = Lw.nchunk;
+    b.rsum = (double*)(w + Lw.rsum);
+    b.pmax = (double*)(w + Lw.pmax);
+    b.diag = (double*)(w + Lw.diag);
+    launch_metrics(X, x_dtype == FR_BF16, prob->r, prob->e, prob->n_users, prob->n_items, prob->m,
+                   b, out, envy, imp, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
 fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const double* imp,
                       double gF, float* dC, float* dr, int32_t checkpoint_every, void* ws,
                       size_t ws_bytes, void* stream) {

@@ -11,19 +11,21 @@
 // lane-local; the column half-step needs the sum over the team's rows.
 //
 // Arithmetic.  Log-domain, base 2: with gamma_k = g_k / (eps ln 2) and the
-// cost exponent z_ik = -c_ik / (eps ln 2) + gamma_k (one FMA), one iteration is
-//   P_ik   = 2^(z_ik - S_i) / s_i,  s_i = sum_k 2^(z_ik - S_i)   (row softmax)
+// scaled cost a_ik = -c_ik / (eps ln 2) - o_i, one iteration is
+//   P_ik   = 2^(a_ik + gamma_k) / s_i,  s_i = sum_k 2^(a_ik + gamma_k)   (row softmax)
 //   sig_k  = sum_i P_ik
 //   gamma_k += log2 b_k - log2 sig_k        (b = 1 ... 1, I-m+1)
 // which is the textbook pair of LSE half-steps with a single exponential per
-// cell.  The plan is X_ik = 2^(z^T_ik + phi_i), phi_i = -(S_i + log2 s_i) from
-// the last row half-step.
+// cell.  The plan is X_ik = 2^(a_ik + gamma^T_k + phi_i), phi_i = -log2 s_i
+// from the last row half-step.
 //
-// Row shift.  Any S_i gives the same P as long as 2^(z - S_i) stays in range.
-// The first row half-step uses the exact row maximum; later ones reuse the
-// row's log-sum-exp from the previous half-step, which moves only by the
-// change of the column potentials, and so skip the max pass.  A row whose sum
-// s_i leaves [2^-16, 2^16] (or is not finite) is redone with its exact max.
+// Row centring.  A constant added to a row of the costs leaves every P and X
+// unchanged (the row softmax absorbs it), so the registers hold each row of
+// scaled costs minus an offset o_i chosen to keep 2^(a + gamma) in range: the
+// row maximum at load, and again whenever a row's sum s_i leaves
+// [2^-16, 2^16] (or is not finite), when the row is re-centred on its current
+// maximum of a + gamma and redone.  The row potential in cost units is then
+// (phi_i - o_i) eps ln 2.
 //
 // Column sums.  Teams narrower than a wave all-reduce every column with DPP
 // row butterflies and the gfx950 row swaps.  Teams of whole waves use a
@@ -238,37 +240,58 @@ __device__ __forceinline__ void spread_owned(float x, float (&v)[MP]) {
 }
 
 // ---------------------------------------------------------------------------
-// Exponentials of one row: e_k = 2^(c_k c2 + gam_k - sh), s = sum_k e_k.
-// sh is S unless `exact` or the sum leaves range; returns sh.
+// Re-centres a row of scaled costs on its current maximum of a + gam if
+// `need`; called by the whole wave (rows that do not need it subtract 0), so
+// that the rare re-centring stays outside divergent control flow.
 template <int MP>
-__device__ __forceinline__ float row_exp(const float (&c)[MP], const float (&gam)[MP], float c2,
-                                         float S, bool exact, float (&e)[MP], float& s) {
-    if (!exact) {
+__device__ __forceinline__ void recentre(float (&a)[MP], const float (&gam)[MP], float& off,
+                                         bool need) {
+    const float one = opaque(1.f);
+    float mx[4] = {kNeg, kNeg, kNeg, kNeg};
 #pragma unroll
-        for (int k = 0; k < MP; ++k) e[k] = ex2(fmaf(c[k], c2, gam[k]) - S);
-        s = Tree<MP>::sum(e);
-        if (s >= kShiftLo && s <= kShiftHi) return S;
-    }
-    const float c2m = opaque(c2);
+    for (int k = 0; k < MP; ++k) mx[k & 3] = fmaxf(mx[k & 3], fmaf(a[k], one, gam[k]));
+    const float M = need ? fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3])) : 0.f;
 #pragma unroll
-    for (int k = 0; k < MP; ++k) e[k] = fmaf(c[k], c2m, gam[k]);
-    const float sh = Tree<MP>::max(e);
-#pragma unroll
-    for (int k = 0; k < MP; ++k) e[k] = ex2(e[k] - sh);
-    s = Tree<MP>::sum(e);
-    return sh;
+    for (int k = 0; k < MP; ++k) a[k] -= M;
+    off += M;
 }
 
-// s = sum_k e_k and, if GH, d = sum_k e_k gh_k for shift sh, without keeping
-// the exponentials.  Four partial sums shorten the dependency chains.
-template <int MP, bool GH>
-__device__ __forceinline__ void row_sums(const float (&c)[MP], const float (&gam)[MP],
-                                         const float (&gh)[MP], float c2, float sh, float& s,
-                                         float& d) {
+__device__ __forceinline__ bool in_range(float s) { return s >= kShiftLo && s <= kShiftHi; }
+
+// True on every lane if any lane of the wave has `bad` set.
+__device__ __forceinline__ bool wave_any(bool bad) { return __builtin_amdgcn_ballot_w64(bad) != 0; }
+
+// Exponentials of one row: e_k = 2^(a_k + gam_k), s = sum_k e_k; the row is
+// re-centred first if the sum leaves range.
+template <int MP>
+__device__ __forceinline__ void row_exp(float (&a)[MP], const float (&gam)[MP], float (&e)[MP],
+                                        float& s, float& off) {
+#pragma unroll
+    for (int k = 0; k < MP; ++k) e[k] = ex2(a[k] + gam[k]);
+    s = Tree<MP>::sum(e);
+    const bool bad = !in_range(s);
+    if (wave_any(bad)) {
+        recentre<MP>(a, gam, off, bad);
+        const float one = opaque(1.f);
+#pragma unroll
+        for (int k = 0; k < MP; ++k) e[k] = ex2(fmaf(a[k], one, gam[k]));
+        s = Tree<MP>::sum(e);
+    }
+}
+
+// s = sum_k e_k and, if GH, d = sum_k e_k gh_k, without keeping the
+// exponentials (e_k = 2^(a_k one + gam_k); one is 1, passed opaque so that
+// separate passes do not share their products).  Four partial sums shorten
+// the dependency chains.
+template <int MP, bool GH, bool SHIFT = false>
+__device__ __forceinline__ void row_sums(const float (&a)[MP], const float (&gam)[MP],
+                                         const float (&gh)[MP], float one, float& s, float& d,
+                                         float sh = 0.f) {
     float ps[4] = {0.f, 0.f, 0.f, 0.f}, pd[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < MP; ++k) {
-        const float e = ex2(fmaf(c[k], c2, gam[k]) - sh);
+        const float z = fmaf(a[k], one, gam[k]);
+        const float e = ex2(SHIFT ? z - sh : z);
         ps[k & 3] += e;
         if (GH) pd[k & 3] = fmaf(e, gh[k], pd[k & 3]);
     }
@@ -277,20 +300,34 @@ __device__ __forceinline__ void row_sums(const float (&c)[MP], const float (&gam
 }
 
 template <int MP, bool GH>
-__device__ __forceinline__ float row_stats(const float (&c)[MP], const float (&gam)[MP],
-                                           const float (&gh)[MP], float c2, float S, bool exact,
-                                           float& s, float& d) {
-    if (!exact) {
-        row_sums<MP, GH>(c, gam, gh, c2, S, s, d);
-        if (s >= kShiftLo && s <= kShiftHi) return S;
+__device__ __forceinline__ void row_stats(float (&a)[MP], const float (&gam)[MP],
+                                          const float (&gh)[MP], float& s, float& d, float& off) {
+    row_sums<MP, GH>(a, gam, gh, 1.f, s, d);
+    const bool bad = !in_range(s);
+    if (wave_any(bad)) {
+        recentre<MP>(a, gam, off, bad);
+        row_sums<MP, GH>(a, gam, gh, opaque(1.f), s, d);
     }
-    const float c2m = opaque(c2);
-    float mx[4] = {kNeg, kNeg, kNeg, kNeg};
+}
+
+// Variant that leaves the costs alone and shifts instead: e_k =
+// 2^(a_k + gam_k - sh), with sh kept per row across calls and reset to the
+// row's current maximum when the sum leaves range.  Used where the registers
+// cannot afford rewriting the costs (the recompute backward).
+template <int MP, bool GH>
+__device__ __forceinline__ void row_stats_shift(const float (&a)[MP], const float (&gam)[MP],
+                                                const float (&gh)[MP], float& s, float& d,
+                                                float& sh) {
+    row_sums<MP, GH, true>(a, gam, gh, 1.f, s, d, sh);
+    const bool bad = !in_range(s);
+    if (wave_any(bad)) {
+        const float one = opaque(1.f);
+        float mx[4] = {kNeg, kNeg, kNeg, kNeg};
 #pragma unroll
-    for (int k = 0; k < MP; ++k) mx[k & 3] = fmaxf(mx[k & 3], fmaf(c[k], c2m, gam[k]));
-    const float sh = fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3]));
-    row_sums<MP, GH>(c, gam, gh, opaque(c2), sh, s, d);
-    return sh;
+        for (int k = 0; k < MP; ++k) mx[k & 3] = fmaxf(mx[k & 3], fmaf(a[k], one, gam[k]));
+        if (bad) sh = fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3]));
+        row_sums<MP, GH, true>(a, gam, gh, opaque(1.f), s, d, sh);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -348,40 +385,46 @@ __device__ __forceinline__ void put_gamma(float* dst, const float (&gam)[MP],
 
 // ---------------------------------------------------------------------------
 // Forward row half-step.  Keeps one row of exponentials: acc gets the lane's
-// column partials sum_i P_ik.  S: shifts in, row log-sum-exps out.
+// column partials sum_i P_ik; S the rows' log2 s_i.
 template <int MP, int R>
-__device__ __forceinline__ void row_pass(const float (&c)[R][MP], const float (&om)[R],
-                                         const float (&gam)[MP], float c2, bool exact,
-                                         float (&acc)[MP], float (&S)[R]) {
+__device__ __forceinline__ void row_pass(float (&c)[R][MP], const float (&om)[R],
+                                         const float (&gam)[MP], float (&acc)[MP], float (&S)[R],
+                                         float (&off)[R]) {
 #pragma unroll
     for (int k = 0; k < MP; ++k) acc[k] = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float e[MP], s;
-        const float sh = row_exp<MP>(c[j], gam, c2, S[j], exact, e, s);
+        row_exp<MP>(c[j], gam, e, s, off[j]);
         const float w = om[j] * rcp(s);
 #pragma unroll
         for (int k = 0; k < MP; ++k) acc[k] = fmaf(e[k], w, acc[k]);
-        S[j] = sh + lg2(s);
+        S[j] = lg2(s);
     }
 }
 
 // Recompute variant (wide teams): row sums first, then the column partials
 // chunk by chunk, each chunk scattered as soon as it is complete.
-template <int MP, int R>
-__device__ __forceinline__ void row_pass_recomp(const float (&c)[R][MP], const float (&om)[R],
-                                                const float (&gam)[MP], float c2, bool exact,
-                                                float (&q)[n_slots(MP)], float (&S)[R]) {
-    float w[R], sh[R];
+// With SHIFT the costs are left alone and sh (per row, kept across calls)
+// shifts the exponents instead of re-centring (used inside the recompute
+// backward, whose registers cannot afford rewriting the costs).
+template <int MP, int R, bool SHIFT = false>
+__device__ __forceinline__ void row_pass_recomp(float (&c)[R][MP], const float (&om)[R],
+                                                const float (&gam)[MP], float (&q)[n_slots(MP)],
+                                                float (&S)[R], float (&off)[R]) {
+    float w[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float s, d;
-        sh[j] = row_stats<MP, false>(c[j], gam, gam, c2, S[j], exact, s, d);
+        if constexpr (SHIFT)
+            row_stats_shift<MP, false>(c[j], gam, gam, s, d, off[j]);
+        else
+            row_stats<MP, false>(c[j], gam, gam, s, d, off[j]);
         w[j] = om[j] * rcp(s);
-        S[j] = sh[j] + lg2(s);
+        S[j] = lg2(s);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const float c2p = opaque(c2);
+    const float one = opaque(1.f);
     for_chunks<MP>([&](auto ch) {
         constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
         float v[ci.n];
@@ -392,7 +435,8 @@ __device__ __forceinline__ void row_pass_recomp(const float (&c)[R][MP], const f
 #pragma unroll
             for (int kk = 0; kk < ci.n; ++kk) {
                 const int k = ci.k0 + kk;
-                v[kk] = fmaf(ex2(fmaf(c[j][k], c2p, gam[k]) - sh[j]), w[j], v[kk]);
+                const float z = fmaf(c[j][k], one, gam[k]);
+                v[kk] = fmaf(ex2(SHIFT ? z - off[j] : z), w[j], v[kk]);
             }
         }
         scatter_chunk<MP, decltype(ch)::value>(v, q);
@@ -420,40 +464,51 @@ __device__ __forceinline__ void col_update_wide(float (&q)[n_slots(MP)], float (
 }
 
 // One forward Sinkhorn iteration of a team.
-template <int MP, int R, bool WIDE, bool RECOMP>
-__device__ __forceinline__ void fwd_iter(const float (&c)[R][MP], const float (&om)[R],
-                                         float (&gam)[MP], float c2, bool exact, float (&S)[R],
+template <int MP, int R, bool WIDE, bool RECOMP, bool SHIFT = false>
+__device__ __forceinline__ void fwd_iter(float (&c)[R][MP], const float (&om)[R],
+                                         float (&gam)[MP], float (&S)[R], float (&off)[R],
                                          Cols<MP, WIDE>& cs, int m, const Team& tm, float* red,
                                          int par) {
     if constexpr (!WIDE) {
         float acc[MP];
-        row_pass<MP, R>(c, om, gam, c2, exact, acc, S);
+        row_pass<MP, R>(c, om, gam, acc, S, off);
         col_update<MP>(acc, gam, cs, m, tm);
     } else {
         float q[n_slots(MP)];
         if constexpr (RECOMP) {
-            row_pass_recomp<MP, R>(c, om, gam, c2, exact, q, S);
+            row_pass_recomp<MP, R, SHIFT>(c, om, gam, q, S, off);
         } else {
             float acc[MP];
-            row_pass<MP, R>(c, om, gam, c2, exact, acc, S);
+            row_pass<MP, R>(c, om, gam, acc, S, off);
             scatter_all<MP>(acc, q);
         }
         col_update_wide<MP>(q, gam, cs, tm, red, par);
     }
 }
 
+// Loads the lane's rows of C as centred scaled costs a_ik = c_ik c2 - o_i,
+// o_i = max_k c_ik c2 (padded columns repeat the last cost; their potential
+// kNeg zeroes them).
 template <int MP, int R>
 __device__ __forceinline__ void load_costs(const float* C, int64_t u, bool active, const Team& tm,
-                                           int I, int m, float (&c)[R][MP], float (&om)[R]) {
+                                           int I, int m, float c2, float (&c)[R][MP],
+                                           float (&om)[R], float (&off)[R]) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int i = tm.lt + j * tm.L;
         const bool valid = active && i < I;
         om[j] = valid ? 1.f : 0.f;
         const float* src = C + (u * I + i) * (int64_t)m;
-        // padded columns repeat the last cost; their potential kNeg zeroes them
+        float t[MP];
 #pragma unroll
-        for (int k = 0; k < MP; ++k) c[j][k] = valid ? src[k < m ? k : m - 1] : 0.f;
+        for (int k = 0; k < MP; ++k) {
+            c[j][k] = valid ? src[k < m ? k : m - 1] : 0.f;
+            t[k] = c[j][k] * c2;
+        }
+        const float M = Tree<MP>::max(t);
+#pragma unroll
+        for (int k = 0; k < MP; ++k) c[j][k] = fmaf(c[j][k], c2, -M);
+        off[j] = M;
     }
 }
 
@@ -469,8 +524,8 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
     const int I = a.I, m = a.m;
     float* red = smem + tm.team * (2 * tm.W * MP);
 
-    float c[R][MP], om[R];
-    load_costs<MP, R>(a.C, u, active, tm, I, m, c, om);
+    float c[R][MP], om[R], off[R];
+    load_costs<MP, R>(a.C, u, active, tm, I, m, a.c2, c, om, off);
 
     float gam[MP];
     Cols<MP, WIDE> cs;
@@ -482,7 +537,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
 #pragma unroll
     for (int j = 0; j < R; ++j) S[j] = 0.f;
     for (int t = 1; t <= a.T; ++t) {
-        fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, a.c2, t == 1, S, cs, m, tm, red, t & 1);
+        fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, S, off, cs, m, tm, red, t & 1);
         if (hist) {
             if (t % a.K == 0)
                 put_gamma<MP, WIDE>(hist + (int64_t)(t / a.K) * a.hs, gam, cs, tm);
@@ -499,14 +554,14 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
     for (int j = 0; j < R; ++j) {
         const int i = tm.lt + j * tm.L;
         if (!(active && i < I)) continue;
-        const float phi = -S[j];
+        const float phi = -S[j];   // row potential of the centred costs
         const int64_t row = u * I + i;
         float yy = 0.f;
         if (a.X && a.x_bf16) {
             uint16_t* dst = (uint16_t*)a.X + row * m;
 #pragma unroll
             for (int k = 0; k < MP; ++k) {
-                const float x = ex2(fmaf(c[j][k], a.c2, gam[k]) + phi);
+                const float x = ex2((c[j][k] + gam[k]) + phi);
                 yy = fmaf(ek[k], x, yy);
                 if (k < mo) dst[k] = to_bf16(x);
             }
@@ -514,17 +569,17 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
             float* dst = (float*)a.X + row * m;
 #pragma unroll
             for (int k = 0; k < MP; ++k) {
-                const float x = ex2(fmaf(c[j][k], a.c2, gam[k]) + phi);
+                const float x = ex2((c[j][k] + gam[k]) + phi);
                 yy = fmaf(ek[k], x, yy);
                 if (k < mo) dst[k] = x;
             }
         } else {
 #pragma unroll
             for (int k = 0; k < MP; ++k)
-                yy = fmaf(ek[k], ex2(fmaf(c[j][k], a.c2, gam[k]) + phi), yy);
+                yy = fmaf(ek[k], ex2((c[j][k] + gam[k]) + phi), yy);
         }
         if (a.y) a.y[row] = a.r[row] * yy;
-        if (a.pot) a.pot[u * (int64_t)(I + m) + i] = phi * a.eps_ln2;
+        if (a.pot) a.pot[u * (int64_t)(I + m) + i] = (phi - off[j]) * a.eps_ln2;
     }
     if (a.pot && active && tm.lt == 0) {
 #pragma unroll
@@ -538,16 +593,16 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
 // gh_k = gbar_k / sig^t_k; cb += P (gh + fbar); the lane's share of
 // sum_i P_ik fbar_i goes to acc (or, recompute variant, to the scattered q).
 template <int MP, int R>
-__device__ __forceinline__ void rev_pass(const float (&c)[R][MP], const float (&om)[R],
-                                         const float (&gp)[MP], const float (&gh)[MP], float c2,
+__device__ __forceinline__ void rev_pass(float (&c)[R][MP], const float (&om)[R],
+                                         const float (&gp)[MP], const float (&gh)[MP],
                                          const float (&fb0)[R], bool first, float (&cb)[R][MP],
-                                         float (&acc)[MP], float (&S)[R]) {
+                                         float (&acc)[MP], float (&off)[R]) {
 #pragma unroll
     for (int k = 0; k < MP; ++k) acc[k] = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float e[MP], s;
-        const float sh = row_exp<MP>(c[j], gp, c2, S[j], false, e, s);
+        row_exp<MP>(c[j], gp, e, s, off[j]);
         float pd[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < MP; ++k) pd[k & 3] = fmaf(e[k], gh[k], pd[k & 3]);
@@ -560,28 +615,26 @@ __device__ __forceinline__ void rev_pass(const float (&c)[R][MP], const float (&
             cb[j][k] = fmaf(e[k], fmaf(w, gh[k], aa), cb[j][k]);
             acc[k] = fmaf(e[k], aa, acc[k]);
         }
-        S[j] = sh + lg2(s);
     }
 }
 
 template <int MP, int R>
 __device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const float (&om)[R],
                                                 const float (&gp)[MP], const float (&gh)[MP],
-                                                float c2, const float (&fb0)[R], bool first,
+                                                const float (&fb0)[R], bool first,
                                                 float (&cb)[R][MP], float (&q)[n_slots(MP)],
-                                                float (&S)[R]) {
-    float sh[R], w[R], aa[R];
+                                                float (&sh)[R]) {
+    float w[R], aa[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float s, d;
-        sh[j] = row_stats<MP, true>(c[j], gp, gh, c2, S[j], false, s, d);
+        row_stats_shift<MP, true>(c[j], gp, gh, s, d, sh[j]);
         w[j] = om[j] * rcp(s);
         const float fb = (first ? fb0[j] : 0.f) - w[j] * d;
         aa[j] = w[j] * fb;
-        S[j] = sh[j] + lg2(s);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const float c2p = opaque(c2);
+    const float one = opaque(1.f);
     for_chunks<MP>([&](auto ch) {
         constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
         float v[ci.n];
@@ -592,7 +645,7 @@ __device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const f
 #pragma unroll
             for (int kk = 0; kk < ci.n; ++kk) {
                 const int k = ci.k0 + kk;
-                const float e = ex2(fmaf(c[j][k], c2p, gp[k]) - sh[j]);
+                const float e = ex2(fmaf(c[j][k], one, gp[k]) - sh[j]);
                 cb[j][k] = fmaf(e, fmaf(w[j], gh[k], aa[j]), cb[j][k]);
                 v[kk] = fmaf(e, aa[j], v[kk]);
             }
@@ -613,22 +666,21 @@ __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][M
                                          const float (&rho)[MP], const float (&rg)[R],
                                          float (&fb0)[R], float (&cb)[R][MP],
                                          float (&acc)[WIDE ? 1 : MP], float (&q)[n_slots(MP)],
-                                         float (&S)[R], int64_t u, bool active, const Team& tm) {
+                                         float (&sh)[R], int64_t u, bool active, const Team& tm) {
     const int m = opaque_u(a.m);
     float ek[MP];
 #pragma unroll
     for (int k = 0; k < MP; ++k) ek[k] = (k < m - 1) ? a.e[k] : 0.f;
-    float sh[R], w[R], xe[R];
+    float w[R], xe[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         float s, d;
-        sh[j] = row_stats<MP, false>(c[j], gp, gp, a.c2, 0.f, true, s, d);
+        row_stats_shift<MP, false>(c[j], gp, gp, s, d, sh[j]);
         w[j] = om[j] * rcp(s) * a.inv_eps;
-        S[j] = sh[j] + lg2(s);
         fb0[j] = 0.f;
         xe[j] = 0.f;
     }
-    const float c2p = opaque(a.c2);
+    const float one = opaque(1.f);
     for_chunks<MP>([&](auto ch) {
         constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
         float v[ci.n];
@@ -640,7 +692,7 @@ __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][M
             for (int kk = 0; kk < ci.n; ++kk) {
                 const int k = ci.k0 + kk;
                 // xs = x / eps, gx = G x / eps
-                const float xs = ex2(fmaf(c[j][k], c2p, gp[k]) - sh[j]) * w[j] * rho[k];
+                const float xs = ex2(fmaf(c[j][k], one, gp[k]) - sh[j]) * w[j] * rho[k];
                 const float gx = rg[j] * ek[k] * xs;
                 cb[j][k] = -gx;
                 fb0[j] += gx;
@@ -674,8 +726,8 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     float* seg = smem + tm.team * ((BL + 1) * MP);
     float* red = smem + teams * ((BL + 1) * MP) + tm.team * (2 * tm.W * MP);
 
-    float c[R][MP], om[R];
-    load_costs<MP, R>(a.C, u, active, tm, I, m, c, om);
+    float c[R][MP], om[R], off[R];
+    load_costs<MP, R>(a.C, u, active, tm, I, m, a.c2, c, om, off);
 
     float rg[R];   // gF r_i / Imp_i, so that G_ik = rg_i e_k
 #pragma unroll
@@ -688,15 +740,16 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gam);
 
     const float* hist = active ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
-    float cb[R][MP], fb0[R], Sb[R], Sf[R];
+    float cb[R][MP], fb0[R], Sf[R], sh[R], shf[R];
     float gbar[WIDE ? 1 : MP];   // narrow: every column; wide: the owned column
 #pragma unroll
     for (int k = 0; k < (WIDE ? 1 : MP); ++k) gbar[k] = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         fb0[j] = 0.f;
-        Sb[j] = 0.f;
         Sf[j] = 0.f;
+        sh[j] = 0.f;   // costs are centred at load: start unshifted
+        shf[j] = 0.f;
     }
 
     int par = 0;
@@ -722,7 +775,8 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
             }
             put_gamma<MP, WIDE>(seg, gam, cs, tm);
             for (int qq = 1; qq <= n; ++qq) {
-                fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, a.c2, qq == 1, Sf, cs, m, tm, red, par);
+                fwd_iter<MP, R, WIDE, RECOMP, RECOMP>(c, om, gam, Sf, RECOMP ? shf : off, cs, m, tm,
+                                                      red, par);
                 par ^= 1;
                 put_gamma<MP, WIDE>(seg + qq * MP, gam, cs, tm);
             }
@@ -747,7 +801,7 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
                 for (int k = 0; k < MP; ++k) rho[k] = ex2(sq[k] - gp[k]);   // 1 on padding
                 float acc[WIDE ? 1 : MP];
                 float q[n_slots(MP)];
-                rev_init<MP, R, WIDE>(a, c, om, gp, rho, rg, fb0, cb, acc, q, Sb, u, active, tm);
+                rev_init<MP, R, WIDE>(a, c, om, gp, rho, rg, fb0, cb, acc, q, sh, u, active, tm);
                 if constexpr (WIDE) {
                     gbar[0] = wide_total<MP>(q, tm, cs.col, red, par);
                 } else {
@@ -771,16 +825,16 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
             if constexpr (WIDE) {
                 float q[n_slots(MP)];
                 if constexpr (RECOMP) {
-                    rev_pass_recomp<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, q, Sb);
+                    rev_pass_recomp<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, q, sh);
                 } else {
                     float acc[MP];
-                    rev_pass<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, acc, Sb);
+                    rev_pass<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, acc, off);
                     scatter_all<MP>(acc, q);
                 }
                 gbar[0] = -wide_total<MP>(q, tm, cs.col, red, par);
             } else {
                 float acc[MP];
-                rev_pass<MP, R>(c, om, gp, gh, a.c2, fb0, t == a.T, cb, acc, Sb);
+                rev_pass<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, acc, off);
                 group_allreduce<MP>(acc, tm.L);
 #pragma unroll
                 for (int k = 0; k < MP; ++k) gbar[k] = -acc[k];
@@ -809,15 +863,16 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
             const float g = cb[j][k];
             if (a.dC) a.dC[base + k] = g;
             if (a.Cw) {
+                const float craw = a.C[base + k];   // the registers hold centred scaled costs
                 if (a.rule == 0) {
                     const float gl = -g;
                     const float mo = a.b1 * a.mom[base + k] + (1.f - a.b1) * gl;
                     const float ve = a.b2 * a.vel[base + k] + (1.f - a.b2) * gl * gl;
                     a.mom[base + k] = mo;
                     a.vel[base + k] = ve;
-                    a.Cw[base + k] = c[j][k] - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
+                    a.Cw[base + k] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
                 } else {
-                    a.Cw[base + k] = c[j][k] + a.lr * g;
+                    a.Cw[base + k] = craw + a.lr * g;
                 }
             }
         }

@@ -114,6 +114,21 @@ void launch_impact_batched(const RedDesc* descs, int n_inst, const int2* tab1, i
                            hipStream_t s);
 int impact_item_groups(int I);
 
+// Evaluation metrics (fr_metrics.hip).
+struct MetricsBufs {
+    double* W;          // [U][I] exposure matrix
+    double* partial;    // [nchunk][I] reduction partials
+    int nchunk;
+    double* rsum;       // [I] sum_u r_ui
+    double* pmax;       // [I][tiles] row maxima of E per column tile
+    double* diag;       // [I] E_ii
+    WsHeader* hdr;      // scratch header for the reduction
+};
+int metrics_tiles(int I);
+void launch_metrics(const void* X, int x_bf16, const float* r, const float* e, int64_t U, int I,
+                    int m, const MetricsBufs& b, double* out, double* envy, double* imp,
+                    hipStream_t s);
+
 // Unfused baseline form (fr_plain.hip).
 struct PlainBufs {
     float *fh, *gh, *y, *cbar, *fbar, *fbar0, *gbar;

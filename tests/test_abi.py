@@ -84,6 +84,20 @@ def test_entry_points_reject_null_context(lib):
                         10**9, None) == 1
     assert lib.fr_sync_status(None, 1, None) == 1
     assert lib.fr_set_launch(None, 20, 5, 64, 1) == 1
+    assert lib.fr_metrics(None, ctypes.byref(p), 1, 0, 1, None, None, 1, 10**9, None) == 1
+
+
+def test_metrics_workspace_validation(lib):
+    import paper_2406_10262_amd as fr
+    n = ctypes.c_size_t()
+    assert lib.fr_workspace_bytes_metrics(None, ctypes.byref(n)) == 1
+    assert lib.fr_workspace_bytes_metrics(ctypes.byref(_prob(fr)), None) == 1
+    assert lib.fr_workspace_bytes_metrics(ctypes.byref(_prob(fr, U=0)), ctypes.byref(n)) == 2
+    assert lib.fr_workspace_bytes_metrics(ctypes.byref(_prob(fr, eps=0.0)), ctypes.byref(n)) == 3
+    assert lib.fr_workspace_bytes_metrics(ctypes.byref(_prob(fr)), ctypes.byref(n)) == 0
+    small = n.value
+    assert lib.fr_workspace_bytes_metrics(ctypes.byref(_prob(fr, U=1000)), ctypes.byref(n)) == 0
+    assert n.value > small
 
 
 def test_status_strings(lib):
