@@ -160,6 +160,7 @@ def bench_solve(args, fr, lib, dev, name):
     if args.profile:
         return None
     Fh = res["F_hist"].cpu().numpy()
+    metrics = bench_metrics(fr, ctx, prob, res["X"])
     del res
     nsw = {"F_0": float(Fh[0]), "F_N": float(Fh[-1])}
     ref = None
@@ -182,7 +183,7 @@ def bench_solve(args, fr, lib, dev, name):
               "step": "one full solve (N outer steps + final forward)",
               "cells": cells, "cell_iters_per_step": work}
     out = base_record(args, value, ms_per_step, config)
-    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof})
+    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics})
     if not args.skip_diag:
         out["measured_peaks"] = measured_peaks(lib)
     if not args.skip_plain and name != "C5":
@@ -204,6 +205,30 @@ def bench_solve(args, fr, lib, dev, name):
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline_solve(inst, name, lr)
     return out
+
+
+def bench_metrics(fr, ctx, prob, X):
+    """Evaluation metrics of the final plan (Section 4.1) and the time of the
+    metrics call; the envy contraction E = R^T W is 2 U I^2 FP64 flops on
+    matrix cores (peak 78.6 TFLOP/s), reported as a rate over the whole call
+    (exposure pass, reductions and the GEMM)."""
+    import torch
+    vals = fr.metrics(ctx, prob, X)
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fr.metrics(ctx, prob, X, sync=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 2.0 * prob.U * prob.I * prob.I
+    v = vals.cpu().numpy()
+    return {"user_utility": float(v[0]), "mean_max_envy": float(v[1]),
+            "items_better": float(v[2]), "items_worse": float(v[3]),
+            "ms": ms, "plan_dtype": "bf16" if X.dtype == torch.bfloat16 else "f32",
+            "envy_gemm": {"flops": flops, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                          "peak_tflops": 78.6, "bound": "mfma (FP64)"}}
 
 
 def c5_subsample_error(fr, dev, inst):

@@ -112,7 +112,13 @@ double model_cost(int64_t U, int mp, int L, const FusedEntry& e) {
     } else {
         red = 2.0 * (4.0 * mp + 10.0) + mp + (L > 64 ? 2.0 * (40.0 + L / 64) : 0.0);
     }
-    const double per_wave = e.rows * mp * cell + red;
+    // registers the backward keeps per lane (costs, cost adjoints, and a row
+    // of exponentials or the recompute pass's chunk) against those its launch
+    // bound leaves; every register short costs spill traffic
+    const int budget = std::min(256, 131072 / e.lb);
+    const int need = 2 * e.rows * mp + (e.recomp_b ? 30 : 2 * mp);
+    const double spill = 1.0 + std::max(0, need - budget) / 32.0;
+    const double per_wave = e.rows * mp * cell * spill + red;
     const double waves = (double)U * (L < 64 ? L / 64.0 : (double)(L / 64));
     const double per_simd = waves / 1024.0;
     return std::max(1.0, per_simd) * per_wave * (per_simd <= 1.0 ? 1.25 : 1.0);

@@ -42,9 +42,9 @@ __global__ __launch_bounds__(256) void k_expo(const void* X, int bf16, const flo
 }
 
 // One 64 x 64 tile of E = R^T W per block (4 waves, each 32 x 32 as 2 x 2
-// MFMA blocks of 16 x 16).  MFMA operand layout (16x16x4, 64 lanes): lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[4 (l / 16) + q][l % 16], q < 4.  Epilogue: the tile goes through LDS; the
+// MFMA blocks of 16 x 16).  Operand layout of the FP64 16x16x4 MFMA (64
+// lanes, checked on the device): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[l / 16 + 4 q][l % 16], q < 4.  Epilogue: the tile goes through LDS; the
 // row maxima over the tile's columns go to pmax[i][blockIdx.y], the diagonal
 // (tiles with blockIdx.x == blockIdx.y) to diag.
 __global__ __launch_bounds__(256) void k_envy_gemm(const float* __restrict__ r,
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_envy_gemm(const float* __restrict__ r,
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                Et[wi + 16 * a + 4 * lk + q][wj + 16 * b + lr] = acc[a][b][q];
+                Et[wi + 16 * a + lk + 4 * q][wj + 16 * b + lr] = acc[a][b][q];
     __syncthreads();
 
     // 4 threads per row, 16 columns each, then a max over the 4

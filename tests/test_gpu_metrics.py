@@ -37,7 +37,8 @@ def _check(fr, r, e, Xs, Xd):
     out, envy, imp = out.cpu().numpy(), envy.cpu().numpy(), imp.cpu().numpy()
     rd, ed = r.astype(np.float64), e.astype(np.float64)
     scale = float(np.max(M.envy_matrix(rd, ed, Xd)))
-    assert np.max(np.abs(imp / M.item_impacts(rd, ed, Xd) - 1)) <= TOL
+    imp_ref = M.item_impacts(rd, ed, Xd)
+    assert np.max(np.abs(imp - imp_ref)) <= TOL * np.max(imp_ref)
     assert abs(out[0] / M.user_utility(rd, ed, Xd) - 1) <= TOL
     assert np.max(np.abs(envy - M.item_envy(rd, ed, Xd))) <= TOL * scale
     assert abs(out[1] - M.mean_max_envy(rd, ed, Xd)) <= TOL * scale
