@@ -158,6 +158,7 @@ def bench_solve(args, fr, lib, dev, name):
     value = work * args.steps / dt
     print(f"bench: fused {ms_per_step:.2f} ms/solve, {value:.4e} cell-iters/s", flush=True)
     if args.profile:
+        bench_metrics(fr, ctx, prob, res["X"])
         return None
     Fh = res["F_hist"].cpu().numpy()
     metrics = bench_metrics(fr, ctx, prob, res["X"])
