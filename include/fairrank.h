@@ -87,6 +87,11 @@ typedef struct {
     int32_t checkpoint_every; /* K: Sinkhorn potentials kept every K iterations for
                                  the reverse sweep (1 = keep all, no recomputation;
                                  0 = let the library choose)                       */
+    double grad_tol;          /* t of Algorithm 1: ascend only while ||dF/dC||_F > t;
+                                 0 = off (exactly outer_steps updates).  With t > 0
+                                 the gradient goes through the workspace, its norm
+                                 is tested in FP64, and after a stop C (and so F)
+                                 no longer changes                                 */
 } fr_optim;
 
 /* ---------------------------------------------------------------- context */
@@ -201,6 +206,14 @@ fr_status fr_sync_status(fr_ctx* ctx, void* ws, void* stream);
 
 /* Static description of a status code. */
 const char* fr_status_string(fr_status s);
+
+/* Adam's step count held in the workspace after fr_solve / fr_solve_plain:
+ * start_step plus the number of updates applied (fewer than outer_steps when
+ * the gradient-norm test of Algorithm 1 stopped the loop), and the norm
+ * ||dF/dC||_F of the last gradient tested (0 when grad_tol was 0).
+ * Synchronises the stream; out pointers are host memory. */
+fr_status fr_solve_progress(fr_ctx* ctx, void* ws, void* stream, int64_t* steps,
+                            double* last_gnorm);
 
 /* Launch configuration of the fused kernels for plans of a given shape:
  * lanes per consumer (1..64 as a power of two, or a multiple of 64 up to

@@ -63,7 +63,7 @@ def _load():
             lib.fro_adam.argtypes = [i64, P, P, P, P, dbl, dbl, dbl, dbl, i64]
             lib.fro_gd.argtypes = [i64, P, P, dbl]
             lib.fro_solve.argtypes = [i64, i32, i32, P, P, dbl, i32, i32, i32, dbl, dbl, dbl,
-                                      dbl, P, P, P, i64, P, P, P]
+                                      dbl, P, P, P, i64, P, P, P, dbl, P, P]
             lib.fro_num_threads.restype = i32
             _lib = lib
     return _lib
@@ -158,8 +158,11 @@ def gd(C, g, lr):
 
 
 def solve(r, e, eps, T, N, C0=None, rule="adam", lr=None, b1=0.9, b2=0.999, aeps=1e-8,
-          mom=None, vel=None, start_step=0, m=None):
-    """Algorithm 1 with N ascent steps.  Returns dict(C, X, F_hist, imp, mom, vel)."""
+          mom=None, vel=None, start_step=0, m=None, grad_tol=0.0):
+    """Algorithm 1 with at most N ascent steps; with grad_tol = t > 0 the loop
+    ends at the first C whose gradient has ||dF/dC||_F <= t (no update there;
+    the remaining F history repeats its F).  Returns dict(C, X, F_hist, imp,
+    mom, vel, gnorm (norm at each step taken, NaN after a stop), updates)."""
     r, e = _d(r), _d(e)
     U, I = r.shape
     mm = e.shape[0] + 1 if m is None else m
@@ -172,7 +175,11 @@ def solve(r, e, eps, T, N, C0=None, rule="adam", lr=None, b1=0.9, b2=0.999, aeps
     X = np.empty_like(C)
     Fh = np.empty(N + 1)
     imp = np.empty(I)
+    gn = np.full(max(N, 1), np.nan)
+    upd = ctypes.c_int64()
     _ok(_load().fro_solve(U, I, mm, _p(r), _p(e), float(eps), int(T), int(N), ri, float(lr),
                           float(b1), float(b2), float(aeps), _p(C), _p(mom), _p(vel),
-                          int(start_step), _p(X), _p(Fh), _p(imp)), "solve")
-    return {"C": C, "X": X, "F_hist": Fh, "imp": imp, "mom": mom, "vel": vel}
+                          int(start_step), _p(X), _p(Fh), _p(imp), float(grad_tol), _p(gn),
+                          ctypes.byref(upd)), "solve")
+    return {"C": C, "X": X, "F_hist": Fh, "imp": imp, "mom": mom, "vel": vel, "gnorm": gn[:N],
+            "updates": int(upd.value)}

@@ -327,17 +327,21 @@ ORC_EXPORT int fro_gd(int64_t n, double* C, const double* grad, double lr) {
     return 0;
 }
 
-/* Algorithm 1 with a fixed number of ascent steps N:
+/* Algorithm 1 with at most N ascent steps:
  *   for n = 0..N: X = Sinkhorn_T(C); F_hist[n] = F(X); if n == N stop;
- *                 grad = dF/dC; C <- update(C, grad).
- * rule 0 = Adam (mom, vel in/out; Adam step count start_step + n + 1),
+ *                 grad = dF/dC; if grad_tol > 0 and ||grad||_F <= grad_tol
+ *                 stop (the loop condition of Algorithm 1); C <- update(C, grad).
+ * After a stop C no longer changes, so F_hist[n+1..N] repeat F_hist[n].
+ * rule 0 = Adam (mom, vel in/out; Adam step count start_step + updates + 1),
  * rule 1 = gradient ascent (mom, vel unused).
- * Outputs: C in place (C_N), X_out = X(C_N) (optional), F_hist [N+1],
- * imp_out = Imp(X(C_N)) (optional). */
+ * Outputs: C in place, X_out = X(C) (optional), F_hist [N+1], imp_out = Imp
+ * (optional), gnorm_hist [N] = ||grad||_F of each step taken (optional),
+ * updates_out = number of updates applied (optional). */
 ORC_EXPORT int fro_solve(int64_t U, int I, int m, const double* r, const double* e, double eps,
                          int T, int N, int rule, double lr, double b1, double b2, double aeps,
                          double* C, double* mom, double* vel, int64_t start_step,
-                         double* X_out, double* F_hist, double* imp_out) {
+                         double* X_out, double* F_hist, double* imp_out, double grad_tol,
+                         double* gnorm_hist, int64_t* updates_out) {
     if (check_shape(U, I, m) || !(eps > 0) || T < 1 || N < 0 || !r || !e || !C || !F_hist)
         return -1;
     if (rule == 0 && (!mom || !vel)) return -1;
@@ -347,17 +351,33 @@ ORC_EXPORT int fro_solve(int64_t U, int I, int m, const double* r, const double*
     double* imp = (double*)malloc(sizeof(double) * I);
     if (!X || !grad || !imp) { free(X); free(grad); free(imp); return -2; }
     int err = 0;
+    int64_t updates = 0;
+    int stopped = 0;
     for (int step = 0; step <= N; ++step) {
+        if (stopped) {   /* the loop of Algorithm 1 has ended: C and F stay */
+            F_hist[step] = F_hist[step - 1];
+            continue;
+        }
         if ((err = fro_forward(U, I, m, C, eps, T, X, NULL, NULL))) break;
         fro_impact(U, I, m, r, e, X, imp);
         F_hist[step] = fro_nsw(I, imp);
         if (step == N) break;
         if ((err = fro_grad(U, I, m, r, e, eps, T, C, imp, grad, NULL))) break;
+        /* stopping test of Algorithm 1: ascend only while ||dF/dC||_F > t */
+        double g2 = 0.0;
+        for (size_t q = 0; q < n; ++q) g2 += grad[q] * grad[q];
+        if (gnorm_hist) gnorm_hist[step] = sqrt(g2);
+        if (grad_tol > 0.0 && sqrt(g2) <= grad_tol) {
+            stopped = 1;
+            continue;
+        }
         if (rule == 0)
-            fro_adam((int64_t)n, C, mom, vel, grad, lr, b1, b2, aeps, start_step + step + 1);
+            fro_adam((int64_t)n, C, mom, vel, grad, lr, b1, b2, aeps, start_step + updates + 1);
         else
             fro_gd((int64_t)n, C, grad, lr);
+        ++updates;
     }
+    if (updates_out) *updates_out = updates;
     if (!err) {
         if (X_out) memcpy(X_out, X, sizeof(double) * n);
         if (imp_out) memcpy(imp_out, imp, sizeof(double) * I);

@@ -53,7 +53,8 @@ class _Problem(ctypes.Structure):
 class _Optim(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
-                ("outer_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32)]
+                ("outer_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
+                ("grad_tol", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -93,11 +94,13 @@ def load():
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.fr_workspace_bytes_metrics.argtypes = [PP, ctypes.POINTER(SZ)]
+    lib.fr_solve_progress.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)]
     lib.fr_metrics.argtypes = [P, PP, P, ctypes.c_int, P, P, P, P, SZ, P]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
-                 "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics"):
+                 "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics",
+                 "fr_solve_progress"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -209,9 +212,9 @@ def _f32(t: torch.Tensor, shape, name):
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {tuple(shape)}")
 
 
-def _optim(rule, lr, beta1, beta2, adam_eps, N, K) -> _Optim:
+def _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol=0.0) -> _Optim:
     return _Optim(FR_ADAM if rule == "adam" else FR_GD, float(lr), float(beta1), float(beta2),
-                  float(adam_eps), int(N), int(K))
+                  float(adam_eps), int(N), int(K), float(grad_tol))
 
 
 def workspace_bytes(prob: Problem, K: int = 1) -> int:
@@ -316,7 +319,7 @@ def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF
 
 
 def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, start_step, K,
-           want_X, x_dtype, plain):
+           want_X, x_dtype, plain, grad_tol=0.0):
     U, I, m = prob.U, prob.I, prob.m
     dev = ctx.device
     C = torch.zeros((U, I, m), dtype=torch.float32, device=dev) if C0 is None else C0.clone()
@@ -331,7 +334,7 @@ def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, sta
         X = torch.empty((U, I, m), dtype=torch.bfloat16 if x_dtype == "bf16" else torch.float32,
                         device=dev)
     Fh = torch.empty(N + 1, dtype=torch.float64, device=dev)
-    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K)
+    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol)
     p = prob.c()
     n = ctypes.c_size_t()
     if plain:
@@ -344,24 +347,31 @@ def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, sta
     _check(fn(ctx.handle, ctypes.byref(p), ctypes.byref(o), _ptr(C), _ptr(mom), _ptr(vel),
               int(start_step), _ptr(X), FR_BF16 if x_dtype == "bf16" else FR_F32, _ptr(Fh),
               _ptr(ws), ws.numel(), _stream(dev)), "fr_solve_plain" if plain else "fr_solve")
-    return {"C": C, "X": X, "F_hist": Fh, "mom": mom, "vel": vel}
+    steps, gn = ctypes.c_int64(), ctypes.c_double()
+    _check(load().fr_solve_progress(ctx.handle, _ptr(ws), _stream(dev), ctypes.byref(steps),
+                                    ctypes.byref(gn)), "fr_solve_progress")
+    return {"C": C, "X": X, "F_hist": Fh, "mom": mom, "vel": vel,
+            "updates": int(steps.value) - int(start_step), "last_gnorm": float(gn.value)}
 
 
 def solve(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,
           beta2: float = 0.999, adam_eps: float = 1e-8, C0=None, mom=None, vel=None,
-          start_step: int = 0, K: int = 0, want_X: bool = True, x_dtype: str = "f32"):
-    """fr_solve: Algorithm 1 with N ascent steps (captured as a HIP graph)."""
+          start_step: int = 0, K: int = 0, want_X: bool = True, x_dtype: str = "f32",
+          grad_tol: float = 0.0):
+    """fr_solve: Algorithm 1 with at most N ascent steps (captured as a HIP
+    graph); grad_tol = t > 0 ends the loop at the first ||dF/dC||_F <= t.
+    The result's "updates" counts the updates applied."""
     return _solve(load().fr_solve, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel,
-                  start_step, K, want_X, x_dtype, False)
+                  start_step, K, want_X, x_dtype, False, grad_tol)
 
 
 def solve_plain(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam",
                 beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8, C0=None,
                 mom=None, vel=None, start_step: int = 0, want_X: bool = True,
-                x_dtype: str = "f32"):
+                x_dtype: str = "f32", grad_tol: float = 0.0):
     """fr_solve_plain: the unfused baseline form (one launch per half-iteration)."""
     return _solve(load().fr_solve_plain, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom,
-                  vel, start_step, 1, want_X, x_dtype, True)
+                  vel, start_step, 1, want_X, x_dtype, True, grad_tol)
 
 
 def solve_batched(ctx: Context, probs, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,

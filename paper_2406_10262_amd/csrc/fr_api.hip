@@ -184,13 +184,14 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t hdr, imp, partial, y, hist, total;
+    size_t hdr, imp, partial, y, hist, grad, gpart, total;
     int nchunk, nck, hs;
 };
 
 int n_checkpoints(int T, int K) { return (T + K - 1) / K + 1; }
 
-Layout layout(const fr_problem* p, int K) {
+// tol: room for the gradient and its norm partials (gradient-norm stop).
+Layout layout(const fr_problem* p, int K, bool tol = false) {
     Layout L;
     const int64_t U = p->n_users;
     const int I = p->n_items;
@@ -208,6 +209,14 @@ Layout layout(const fr_problem* p, int K) {
     off += align_up(sizeof(float) * (size_t)U * I);
     L.hist = off;
     off += align_up(sizeof(float) * (size_t)U * L.nck * L.hs);
+    L.grad = L.gpart = off;
+    if (tol) {
+        const int64_t n = U * (int64_t)I * p->m;
+        L.grad = off;
+        off += align_up(sizeof(float) * (size_t)n);
+        L.gpart = off;
+        off += align_up(sizeof(double) * (size_t)gnorm_blocks(n));
+    }
     L.total = off;
     return L;
 }
@@ -225,7 +234,7 @@ fr_status check_problem(const fr_problem* p) {
 int resolve_k(int K) { return K <= 0 ? 1 : K; }
 
 struct PlainLayout {
-    size_t hdr, imp, partial, y, fh, gh, cbar, fbar, fbar0, gbar, total;
+    size_t hdr, imp, partial, y, fh, gh, cbar, fbar, fbar0, gbar, gpart, total;
     int nchunk;
 };
 
@@ -250,6 +259,7 @@ PlainLayout plain_layout(const fr_problem* p) {
     L.fbar = take(sizeof(float) * (size_t)U * I);
     L.fbar0 = take(sizeof(float) * (size_t)U * I);
     L.gbar = take(sizeof(float) * (size_t)U * m);
+    L.gpart = take(sizeof(double) * (size_t)gnorm_blocks(U * (int64_t)I * m));
     L.total = off;
     return L;
 }
@@ -262,6 +272,7 @@ fr_status check_optim(const fr_optim* o, const float* mom, const float* vel, int
         (!(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f) ||
          !(o->adam_eps >= 0.f)))
         return FR_E_PARAM;
+    if (!(o->grad_tol >= 0.0) || !isfinite(o->grad_tol)) return FR_E_PARAM;
     return FR_OK;
 }
 
@@ -323,9 +334,12 @@ fr_status launch_bwd(const Shape& sh, const BwdArgs& a, hipStream_t s) {
 __global__ void k_init_header(WsHeader* h, int64_t step) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         h->flags = 0;
+        h->stopped = 0;
         h->step = step;
         for (int q = 0; q < 8; ++q) h->work[q] = 0;
         h->F = 0.0;
+        h->rep = 0;
+        h->gnorm = 0.0;
     }
 }
 
@@ -568,7 +582,7 @@ fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size
     fr_status st = check_problem(prob);
     if (st) return st;
     const int K = optim ? resolve_k(optim->checkpoint_every) : 1;
-    *out = layout(prob, K).total;
+    *out = layout(prob, K, optim && optim->grad_tol > 0.0).total;
     return FR_OK;
 }
 
@@ -761,7 +775,8 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     if (!C || !F_hist || !ws) return FR_E_NULL;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
     const int K = resolve_k(optim->checkpoint_every);
-    const Layout Lw = layout(prob, K);
+    const bool tol = optim->grad_tol > 0.0;
+    const Layout Lw = layout(prob, K, tol);
     if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
     Shape sh;
     if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, K, &sh))) return st;
@@ -770,6 +785,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     if (!stream) FR_TRY(hipStreamSynchronize(nullptr));
     char* w = (char*)ws;
     WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
+    const int64_t ncell = prob->n_users * (int64_t)prob->n_items * prob->m;
     double* imp = (double*)(w + Lw.imp);
     double* partial = (double*)(w + Lw.partial);
     float* y = (float*)(w + Lw.y);
@@ -797,9 +813,27 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     b.b1 = optim->beta1;
     b.b2 = optim->beta2;
     b.aeps = optim->adam_eps;
+    if (tol) {
+        // Algorithm 1's loop test: the backward writes the gradient, its norm
+        // decides, and every launch of the replayed step is skipped after a stop
+        a.stop = &hdr->stopped;
+        b.stop = &hdr->stopped;
+        b.Cw = nullptr;
+        b.dC = (float*)(w + Lw.grad);
+    }
+    auto outer_step = [&]() {
+        sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+        launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
+                      start_step, hdr, tol ? ADV_REP : ADV_REP_STEP, s);
+        sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+        if (tol)
+            launch_gnorm_update(b.dC, C, adam_m, adam_v, ncell, optim->rule, optim->lr,
+                                optim->beta1, optim->beta2, optim->adam_eps,
+                                (double*)(w + Lw.gpart), optim->grad_tol, hdr, s);
+    };
 
     const int N = optim->outer_steps;
-    if (N > 0 && ctx->timing) {
+    if (N > 0 && ctx->timing && !tol) {
         // direct launches, each fused kernel bracketed by events
         std::vector<hipEvent_t> ev(4 * (size_t)N);
         for (auto& x : ev) FR_TRY(hipEventCreate(&x));
@@ -808,7 +842,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
             sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
             FR_TRY(hipEventRecord(ev[4 * n + 1], s));
             launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
-                          start_step, hdr, 1, s);
+                          start_step, hdr, ADV_REP_STEP, s);
             FR_TRY(hipEventRecord(ev[4 * n + 2], s));
             sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
             FR_TRY(hipEventRecord(ev[4 * n + 3], s));
@@ -829,10 +863,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         FR_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
-        launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
-                      start_step, hdr, 1, s);
-        sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+        outer_step();
         hipError_t ce = hipStreamEndCapture(s, &graph);
         if (ce != hipSuccess) return FR_E_DEVICE;
         ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -845,15 +876,29 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         hipGraphDestroy(graph);
         if (ce != hipSuccess) return FR_E_DEVICE;
     }
-    // final forward: X(C_N) and F_N
+    // final forward: X(C_N) and F_N (also after a stop)
     a.hist = nullptr;
+    a.stop = nullptr;
     a.X = X_out;
     a.x_bf16 = (x_dtype == FR_BF16);
     if ((st = launch_fwd(sh, a, s))) return st;
     launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
-                  start_step, hdr, 0, s);
+                  start_step, hdr, ADV_NONE, s);
     FR_TRY(hipGetLastError());
     return read_flags(hdr, s, false);
+}
+
+fr_status fr_solve_progress(fr_ctx* ctx, void* ws, void* stream, int64_t* steps,
+                            double* last_gnorm) {
+    if (!ctx || !ws) return FR_E_NULL;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    FR_TRY(hipStreamSynchronize(s));
+    WsHeader h;
+    FR_TRY(hipMemcpy(&h, ws, sizeof(WsHeader), hipMemcpyDeviceToHost));
+    if (steps) *steps = h.step;
+    if (last_gnorm) *last_gnorm = h.gnorm;
+    return FR_OK;
 }
 
 fr_status fr_ctx_set_timing(fr_ctx* ctx, int enable) {
@@ -921,17 +966,24 @@ fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* op
     const int64_t U = prob->n_users;
     const int I = prob->n_items, m = prob->m, T = prob->sinkhorn_iters;
     hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, b.hdr, start_step);
+    const bool tol = optim->grad_tol > 0.0;
     for (int n = 0; n < optim->outer_steps; ++n) {
+        // after a gradient-norm stop C no longer changes, so F repeats
         plain_forward(C, prob->r, prob->e, U, I, m, prob->eps, T, b, nullptr, 0, s);
-        launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr, 1,
-                      s);
+        launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr,
+                      tol ? ADV_REP : ADV_REP_STEP, s);
         plain_backward_update(C, prob->r, prob->e, U, I, m, prob->eps, T, b, adam_m, adam_v,
                               optim->rule, optim->lr, optim->beta1, optim->beta2, optim->adam_eps,
-                              s);
+                              !tol, s);
+        if (tol)
+            launch_gnorm_update(b.cbar, C, adam_m, adam_v, U * (int64_t)I * m, optim->rule,
+                                optim->lr, optim->beta1, optim->beta2, optim->adam_eps,
+                                (double*)(w + Lw.gpart), optim->grad_tol, b.hdr, s);
         FR_TRY(hipGetLastError());
     }
     plain_forward(C, prob->r, prob->e, U, I, m, prob->eps, T, b, X_out, x_dtype == FR_BF16, s);
-    launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr, 0, s);
+    launch_impact(b.y, U, I, b.partial, b.nchunk, b.imp, nullptr, F_hist, start_step, b.hdr,
+                  ADV_NONE, s);
     FR_TRY(hipGetLastError());
     return read_flags(b.hdr, s, false);
 }
@@ -958,6 +1010,9 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
                            fr_dtype x_dtype, double* const* F_hist, void* ws, size_t ws_bytes,
                            void* stream) {
     if (!ctx || !optim || !probs || !C || !F_hist || !ws) return FR_E_NULL;
+    // the gradient-norm test of Algorithm 1 is per instance: not offered for
+    // the batched solve
+    if (optim->grad_tol != 0.0) return FR_E_UNSUPPORTED;
     if (n_inst < 1) return FR_E_SHAPE;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
     for (int j = 0; j < n_inst; ++j) {

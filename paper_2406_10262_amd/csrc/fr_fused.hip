@@ -892,6 +892,7 @@ constexpr bool recomp_bwd() { return WIDE && (2 * R * FR_MP + 2 * FR_MP > reg_bu
 template <int MP, int R, int LB, bool WIDE>
 __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
     extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
     fwd_body<MP, R, WIDE, recomp_fwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
                                                      smem);
 }
@@ -899,6 +900,7 @@ __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
 template <int MP, int R, int LB, bool WIDE>
 __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
     extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
     bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
                                                      smem);
 }

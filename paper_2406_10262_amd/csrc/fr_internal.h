@@ -12,10 +12,12 @@ enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_ZERO_IMPACT = 2u };
 // Workspace header (first 256 bytes of every workspace).
 struct WsHeader {
     uint32_t flags;       // FLAG_* bits, sticky until fr_sync_status clears them
-    uint32_t pad0;
-    int64_t step;         // Adam step counter advanced once per outer step
+    int32_t stopped;      // the gradient-norm test of Algorithm 1 ended the loop
+    int64_t step;         // Adam step count (advanced once per update applied)
     uint32_t work[8];     // work-queue counters of the batched kernels
     double F;             // last objective value
+    int64_t rep;          // outer steps recorded in the F history since the start
+    double gnorm;         // ||dF/dC||_F of the last gradient tested
 };
 
 // ---------------------------------------------------------------------------
@@ -29,6 +31,7 @@ struct FwdArgs {
     float* hist;           // [U][nck][hs] base-2 column potentials (or null)
     void* X;               // [U][I][m] plan (or null)
     float* pot;            // [U][I+m] potentials in cost units (or null)
+    const int32_t* stop;   // skip the launch when *stop != 0 (or null)
     int64_t U;
     int I, m, T, K, nck, hs, L, x_bf16;
     float c2;              // -1 / (eps ln 2): exponent scale of a cost
@@ -47,6 +50,7 @@ struct BwdArgs {
     float* mom;            // Adam first moment (or null)
     float* vel;            // Adam second moment (or null)
     const int64_t* step_ptr;  // device Adam step counter (or null: use step_const)
+    const int32_t* stop;      // skip the launch when *stop != 0 (or null)
     int64_t step_const;
     double gF;
     int64_t U;
@@ -92,10 +96,22 @@ FR_MP_CLASSES(FR_DECL_ENTRIES)
 // Reverse-sweep block length when every iterate is kept (K == 1).
 constexpr int kLoadBlock = 32;
 
-// Reductions over consumers (fr_reduce.hip).
+// Reductions over consumers (fr_reduce.hip).  F_hist[hdr->rep] receives F;
+// advance: 0 leaves the counters, ADV_REP advances rep, ADV_REP_STEP rep and
+// the Adam step.
+enum { ADV_NONE = 0, ADV_REP = 1, ADV_REP_STEP = 2 };
 void launch_impact(const float* y, int64_t U, int I, double* partial, int nchunk, double* imp,
                    double* F, double* F_hist, int64_t start_step, WsHeader* hdr, int advance,
                    hipStream_t s);
+
+// Gradient-norm test of Algorithm 1 and the update it guards: ||g||_F in FP64
+// (fixed order); if it is <= tol the loop stops (hdr->stopped), otherwise the
+// Adam step advances and C is updated from g.  Every kernel returns at once
+// once the loop has stopped.
+int gnorm_blocks(int64_t n);
+void launch_gnorm_update(const float* g, float* C, float* mom, float* vel, int64_t n, int rule,
+                         float lr, float b1, float b2, float aeps, double* partial, double tol,
+                         WsHeader* hdr, hipStream_t s);
 void launch_rows_from_plan(const void* X, int x_bf16, const float* r, const float* e, int64_t U,
                            int I, int m, float* y, hipStream_t s);
 int impact_chunks(int64_t U, int I);
@@ -140,6 +156,6 @@ void plain_forward(const float* C, const float* r, const float* e, int64_t U, in
                    float eps, int T, const PlainBufs& b, void* X, int bf16, hipStream_t s);
 void plain_backward_update(float* C, const float* r, const float* e, int64_t U, int I, int m,
                            float eps, int T, const PlainBufs& b, float* mom, float* vel, int rule,
-                           float lr, float b1, float b2, float aeps, hipStream_t s);
+                           float lr, float b1, float b2, float aeps, bool apply, hipStream_t s);
 
 }  // namespace fr

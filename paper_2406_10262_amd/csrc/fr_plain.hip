@@ -230,7 +230,7 @@ void plain_forward(const float* C, const float* r, const float* e, int64_t U, in
 
 void plain_backward_update(float* C, const float* r, const float* e, int64_t U, int I, int m,
                            float eps, int T, const PlainBufs& b, float* mom, float* vel, int rule,
-                           float lr, float b1, float b2, float aeps, hipStream_t s) {
+                           float lr, float b1, float b2, float aeps, bool apply, hipStream_t s) {
     const int64_t rows = U * I;
     const dim3 cgrid((unsigned)U, (unsigned)((m + kColsPerBlock - 1) / kColsPerBlock));
     const float* fT = b.fh + (int64_t)(T - 1) * rows;
@@ -248,8 +248,9 @@ void plain_backward_update(float* C, const float* r, const float* e, int64_t U, 
         hipLaunchKernelGGL(k_rev_row, cgrid, dim3(256), 0, s, C, ft, gp, b.fbar, b.cbar, b.gbar, I,
                            m, eps);
     }
-    hipLaunchKernelGGL(k_update, dim3(nblk(rows * m)), dim3(256), 0, s, C, mom, vel, b.cbar,
-                       rows * m, rule, lr, b1, b2, aeps, &b.hdr->step);
+    if (apply)
+        hipLaunchKernelGGL(k_update, dim3(nblk(rows * m)), dim3(256), 0, s, C, mom, vel, b.cbar,
+                           rows * m, rule, lr, b1, b2, aeps, &b.hdr->step);
 }
 
 }  // namespace fr

@@ -81,9 +81,10 @@ __global__ __launch_bounds__(kFinalThreads) void k_imp_final(const double* __res
         const double Fv = red[0];
         hdr->F = Fv;
         if (F) *F = Fv;
-        const int64_t st = hdr->step;
-        if (F_hist) F_hist[st - start_step] = Fv;
-        if (advance) hdr->step = st + 1;
+        const int64_t rep = hdr->rep;
+        if (F_hist) F_hist[rep] = Fv;
+        if (advance != ADV_NONE) hdr->rep = rep + 1;
+        if (advance == ADV_REP_STEP) hdr->step += 1;
     }
 }
 
@@ -164,7 +165,90 @@ __global__ __launch_bounds__(256) void k_bimp_final(const RedDesc* __restrict__ 
     if (threadIdx.x == 0 && d.F_hist) d.F_hist[hdr->step - start_step] = red[0];
 }
 
+// Gradient-norm test: FP64 sums of squares over fixed chunks, then one block.
+constexpr int kNormPer = 64;   // elements per thread
+__global__ __launch_bounds__(256) void k_gnorm_partial(const float* __restrict__ g, int64_t n,
+                                                       double* __restrict__ partial,
+                                                       const int32_t* stop) {
+    __shared__ double red[256];
+    if (*stop) return;
+    const int64_t base = (int64_t)blockIdx.x * (256 * kNormPer);
+    double sq = 0.0;
+    for (int q = 0; q < kNormPer; ++q) {
+        const int64_t j = base + (int64_t)q * 256 + threadIdx.x;
+        if (j < n) {
+            const double v = (double)g[j];
+            sq += v * v;
+        }
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_gnorm_final(const double* __restrict__ partial, int nb,
+                                                      double tol, WsHeader* hdr) {
+    __shared__ double red[1024];
+    if (hdr->stopped) return;
+    double sq = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024) sq += partial[b];
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double gn = sqrt(red[0]);
+        hdr->gnorm = gn;
+        if (gn <= tol)
+            hdr->stopped = 1;
+        else
+            hdr->step += 1;
+    }
+}
+
+// C += lr g (ascent) or the Adam step on -g (maximisation), unless stopped.
+__global__ __launch_bounds__(256) void k_apply(float* __restrict__ C, float* __restrict__ mom,
+                                               float* __restrict__ vel, const float* __restrict__ g,
+                                               int64_t n, int rule, float lr, float b1, float b2,
+                                               float aeps, const WsHeader* hdr) {
+    if (hdr->stopped) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (rule == 1) {
+        C[j] += lr * g[j];
+        return;
+    }
+    const int64_t st = hdr->step;
+    const float bc1 = (float)(1.0 - pow((double)b1, (double)st));
+    const float bc2 = (float)(1.0 - pow((double)b2, (double)st));
+    const float gl = -g[j];
+    const float mo = b1 * mom[j] + (1.f - b1) * gl;
+    const float ve = b2 * vel[j] + (1.f - b2) * gl * gl;
+    mom[j] = mo;
+    vel[j] = ve;
+    C[j] -= lr * (mo / bc1) / (sqrtf(ve / bc2) + aeps);
+}
+
 }  // namespace
+
+int gnorm_blocks(int64_t n) { return (int)((n + 256 * kNormPer - 1) / (256 * kNormPer)); }
+
+void launch_gnorm_update(const float* g, float* C, float* mom, float* vel, int64_t n, int rule,
+                         float lr, float b1, float b2, float aeps, double* partial, double tol,
+                         WsHeader* hdr, hipStream_t s) {
+    const int nb = gnorm_blocks(n);
+    hipLaunchKernelGGL(k_gnorm_partial, dim3(nb), dim3(256), 0, s, g, n, partial, &hdr->stopped);
+    hipLaunchKernelGGL(k_gnorm_final, dim3(1), dim3(1024), 0, s, (const double*)partial, nb, tol,
+                       hdr);
+    hipLaunchKernelGGL(k_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, mom, vel, g,
+                       n, rule, lr, b1, b2, aeps, (const WsHeader*)hdr);
+}
 
 void launch_impact_batched(const RedDesc* descs, int n_inst, const int2* tab1, int n1,
                            const int2* tab2, int n2, int64_t start_step, WsHeader* hdr,

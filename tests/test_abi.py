@@ -131,3 +131,14 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    fr.load()\nexcept FileNotFoundError:\n    print('raised')\n")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
     assert "raised" in out.stdout, out.stderr
+
+
+def test_gradient_norm_stop_needs_gradient_room(lib):
+    import paper_2406_10262_amd as fr
+    n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+    o = fr._Optim(0, 0.01, 0.9, 0.999, 1e-8, 5, 1)
+    assert lib.fr_workspace_bytes(ctypes.byref(_prob(fr)), ctypes.byref(o), ctypes.byref(n0)) == 0
+    o.grad_tol = 1e-3
+    assert lib.fr_workspace_bytes(ctypes.byref(_prob(fr)), ctypes.byref(o), ctypes.byref(n1)) == 0
+    assert n1.value >= n0.value + 10 * 20 * 5 * 4
+    assert lib.fr_solve_progress(None, 1, None, None, None) == 1

@@ -311,3 +311,25 @@ def test_solve_is_the_plain_loop():
         gC, _ = oracle.grad(r, e, eps, 15, C, imp=imp)
         oracle.adam(C, mom, vel, gC, lr, step=n + 1)
     assert np.array_equal(C, res["C"])
+
+
+def test_gradient_norm_stop_of_algorithm_1():
+    """The loop condition of Algorithm 1: ascend only while ||dF/dC|| > t."""
+    inst = W.config("C1")
+    r, e, eps, T = inst.r, inst.e, float(inst.eps), 30
+    full = oracle.solve(r, e, eps, T, 6, rule="gd", lr=0.5)
+    g = full["gnorm"]
+    assert full["updates"] == 6 and np.all(np.isfinite(g))
+    # t above every norm: stop at C0 = 0, no update, F constant
+    top = oracle.solve(r, e, eps, T, 6, rule="gd", lr=0.5, grad_tol=2 * g.max())
+    assert top["updates"] == 0 and np.all(top["C"] == 0.0)
+    assert np.all(top["F_hist"] == full["F_hist"][0])
+    # t between the running minimum before step j and the norm at step j: j updates
+    j = next(k for k in range(1, 6) if g[k] < g[:k].min())
+    t = 0.5 * (g[j] + g[:j].min())
+    part = oracle.solve(r, e, eps, T, 6, rule="gd", lr=0.5, grad_tol=t)
+    assert part["updates"] == j
+    assert np.array_equal(part["F_hist"][: j + 1], full["F_hist"][: j + 1])
+    assert np.all(part["F_hist"][j + 1:] == full["F_hist"][j])
+    ref = oracle.solve(r, e, eps, T, j, rule="gd", lr=0.5)
+    assert np.array_equal(part["C"], ref["C"]) and np.array_equal(part["X"], ref["X"])
