@@ -9,8 +9,11 @@ with the GPU path (``paper_2406_10262_amd``) and never imports it.
   impacts, NSW, reverse-mode gradient, Adam / gradient ascent, Algorithm 1).
 * ``oracle.brute`` -- NumPy brute-force optima and closed forms for tiny
   instances, used to pin the oracle itself.
+* ``oracle.metrics`` -- the evaluation metrics of a plan.
+* ``oracle.warm`` -- Algorithm 1 on the converged map: warm-started Sinkhorn
+  and the implicit-function gradient.
 """
 from .core import (  # noqa: F401
-    build_oracle, forward, forward_converge, impact, nsw, grad, adam, gd, solve,
+    build_oracle, forward, forward_converge, forward_warm, impact, nsw, grad, adam, gd, solve,
     num_threads, library_path,
 )

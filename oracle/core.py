@@ -57,6 +57,7 @@ def _load():
             lib.fro_forward.argtypes = [i64, i32, i32, P, dbl, i32, P, P, P]
             lib.fro_forward_converge.argtypes = [i64, i32, i32, P, dbl, dbl, i32, P, P, P, P]
             lib.fro_impact.argtypes = [i64, i32, i32, P, P, P, P]
+            lib.fro_forward_warm.argtypes = [i64, i32, i32, P, dbl, P, dbl, i32, P, P, P]
             lib.fro_nsw.argtypes = [i32, P]
             lib.fro_nsw.restype = dbl
             lib.fro_grad.argtypes = [i64, i32, i32, P, P, dbl, i32, P, P, P, P]
@@ -109,6 +110,20 @@ def forward_converge(C, eps, tol=1e-13, cap=100000):
     _ok(_load().fro_forward_converge(U, I, m, _p(C), float(eps), float(tol), int(cap), _p(X),
                                      _p(f), _p(g), _p(its)), "forward_converge")
     return X, f, g, its
+
+
+def forward_warm(C, eps, g0, tol, T_max):
+    """Sinkhorn from column potentials g0 [U][m] until no potential moves by
+    more than tol (log2 units) in an iteration, or T_max iterations.
+    Returns (X, g, iters)."""
+    C = _d(C)
+    U, I, m = C.shape
+    g = _d(g0).copy()
+    X = np.empty_like(C)
+    it = np.empty(U, dtype=np.int32)
+    _ok(_load().fro_forward_warm(U, I, m, _p(C), float(eps), _p(g), float(tol), int(T_max),
+                                 _p(X), None, _p(it)), "forward_warm")
+    return X, g, it
 
 
 def impact(r, e, X):

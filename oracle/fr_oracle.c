@@ -133,6 +133,53 @@ ORC_EXPORT int fro_forward(int64_t U, int I, int m, const double* C, double eps,
     return err;
 }
 
+/* Warm-started forward: for each consumer, iterate from the column
+ * potentials g_io[u] (in/out, [U][m]) until the column half-step changes no
+ * potential by more than tol in log2 units (max_k |g^t_k - g^{t-1}_k| /
+ * (eps ln 2) <= tol), or T_max iterations; tol = 0 runs exactly T_max.
+ * X from the final potentials; iters_out[u] = iterations used (optional),
+ * f_out [U][I] (optional). */
+ORC_EXPORT int fro_forward_warm(int64_t U, int I, int m, const double* C, double eps,
+                                double* g_io, double tol, int T_max, double* X, double* f_out,
+                                int* iters_out) {
+    if (check_shape(U, I, m) || !(eps > 0) || T_max < 1 || !C || !g_io || !X) return -1;
+    int err = 0;
+    const double to_log2 = 1.0 / (eps * log(2.0));
+#pragma omp parallel
+    {
+        double* f = (double*)malloc(sizeof(double) * I);
+        double* gp = (double*)malloc(sizeof(double) * m);
+        double* z = (double*)malloc(sizeof(double) * (I > m ? I : m));
+        if (!f || !gp || !z) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t u = 0; u < U; ++u) {
+                const double* c = C + (size_t)u * I * m;
+                double* g = g_io + (size_t)u * m;
+                int t = 0;
+                for (t = 1; t <= T_max; ++t) {
+                    memcpy(gp, g, sizeof(double) * m);
+                    sinkhorn_iter(I, m, c, eps, f, g, z);
+                    double worst = 0.0;
+                    for (int k = 0; k < m; ++k) {
+                        const double d = fabs(g[k] - gp[k]) * to_log2;
+                        if (d > worst) worst = d;
+                    }
+                    if (tol > 0.0 && worst <= tol) break;
+                }
+                if (t > T_max) t = T_max;
+                plan_from_potentials(I, m, c, eps, f, g, X + (size_t)u * I * m);
+                if (f_out) memcpy(f_out + (size_t)u * I, f, sizeof(double) * I);
+                if (iters_out) iters_out[u] = t;
+            }
+        }
+        free(f); free(gp); free(z);
+    }
+    return err;
+}
+
 /* Forward run to convergence: iterate until the largest row-marginal error of
  * the plan (columns are exact after every column half-step) is below tol, or
  * until cap iterations.  iters_out[u] receives the count used. */
