@@ -92,6 +92,17 @@ typedef struct {
                                  the gradient goes through the workspace, its norm
                                  is tested in FP64, and after a stop C (and so F)
                                  no longer changes                                 */
+    float sinkhorn_tol;       /* 0: the paper's Algorithm 1 (T iterations from g = 0,
+                                 gradient by reverse mode through them).  > 0: the
+                                 converged-map form: each outer step's Sinkhorn
+                                 starts from the previous step's column potentials
+                                 and stops once no potential moves by more than
+                                 sinkhorn_tol (log2 units; at most T iterations),
+                                 and the gradient is the implicit-function gradient
+                                 of the balanced plan (no reverse sweep).  Not for
+                                 fr_solve_plain or fr_solve_batched.               */
+    int32_t cg_iters;         /* converged-map form: conjugate-gradient cap of the
+                                 implicit gradient's m x m solve (0 = 2m + 8)     */
 } fr_optim;
 
 /* ---------------------------------------------------------------- context */
@@ -100,7 +111,9 @@ fr_status fr_ctx_create(int device, fr_ctx** out);
 void fr_ctx_destroy(fr_ctx* ctx);
 
 /* Bytes of workspace every call below needs for this problem (optim may be
- * NULL: then K = 1 and no Adam state).  Written to *out (host). */
+ * NULL: then K = 1 and no Adam state; a positive grad_tol or sinkhorn_tol adds
+ * the room those modes need).  Written to *out (host).  FR_E_PARAM for a
+ * negative or non-finite tolerance or negative cg_iters. */
 fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size_t* out);
 
 /* Prepares a newly allocated workspace (clears its device flags and step
@@ -146,6 +159,20 @@ fr_status fr_metrics(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtyp
                      void* stream);
 
 /* --------------------------------------------------------------- backward */
+/* Value and gradient of the converged map (the converged-map form of
+ * fr_optim.sinkhorn_tol): Sinkhorn from g = 0 until no column potential moves
+ * by more than sinkhorn_tol (log2 units; at most T iterations), Imp and F of
+ * that plan, then gF * dF/dC by the implicit function theorem at the balanced
+ * plan: dF/dc_ik = -(1/eps) x_ik (G_ik - lam_i - mu_k) with (lam, mu) from the
+ * optimality conditions (gauge mu_{m-1} = 0; an m x m Schur system solved by
+ * preconditioned conjugate gradients, at most cg_iters iterations, 0 = 2m + 8),
+ * and dr = gF * dF/dr.  imp [I], F [1], dC [U][I][m]; imp, F and dr optional.
+ * Workspace: fr_workspace_bytes with an optim whose sinkhorn_tol > 0. */
+fr_status fr_grad_converged(fr_ctx* ctx, const fr_problem* prob, const float* C,
+                            float sinkhorn_tol, int32_t cg_iters, double gF, double* imp,
+                            double* F, float* dC, float* dr, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Section 3 ("chain rule"): reverse mode through the T unrolled Sinkhorn
  * iterations.  Given C and the impacts imp [I] of X(C) (from fr_step), writes
  * dC = gF * dF/dC [U][I][m] and, if dr is not NULL, dr = gF * dF/dr [U][I].
@@ -209,11 +236,13 @@ const char* fr_status_string(fr_status s);
 
 /* Adam's step count held in the workspace after fr_solve / fr_solve_plain:
  * start_step plus the number of updates applied (fewer than outer_steps when
- * the gradient-norm test of Algorithm 1 stopped the loop), and the norm
- * ||dF/dC||_F of the last gradient tested (0 when grad_tol was 0).
- * Synchronises the stream; out pointers are host memory. */
+ * the gradient-norm test of Algorithm 1 stopped the loop), the norm
+ * ||dF/dC||_F of the last gradient tested (0 when grad_tol was 0), and, for
+ * the converged-map form, the Sinkhorn iterations used summed over consumers
+ * and forward passes (0 otherwise).  Synchronises the stream; out pointers
+ * are host memory (each optional). */
 fr_status fr_solve_progress(fr_ctx* ctx, void* ws, void* stream, int64_t* steps,
-                            double* last_gnorm);
+                            double* last_gnorm, int64_t* sinkhorn_iters);
 
 /* Launch configuration of the fused kernels for plans of a given shape:
  * lanes per consumer (1..64 as a power of two, or a multiple of 64 up to

@@ -22,6 +22,7 @@ import torch
 __all__ = [
     "load", "library_path", "FairRankError", "Context", "Problem", "step", "nsw",
     "backward", "solve", "solve_plain", "solve_batched", "SinkhornNSW", "sinkhorn_nsw", "metrics",
+    "grad_converged",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +55,8 @@ class _Optim(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
                 ("outer_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
-                ("grad_tol", ctypes.c_double)]
+                ("grad_tol", ctypes.c_double), ("sinkhorn_tol", ctypes.c_float),
+                ("cg_iters", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -94,13 +96,16 @@ def load():
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.fr_workspace_bytes_metrics.argtypes = [PP, ctypes.POINTER(SZ)]
-    lib.fr_solve_progress.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double)]
+    lib.fr_solve_progress.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I64)]
+    lib.fr_grad_converged.argtypes = [P, PP, P, ctypes.c_float, I32, ctypes.c_double, P, P, P, P,
+                                      P, SZ, P]
     lib.fr_metrics.argtypes = [P, PP, P, ctypes.c_int, P, P, P, P, SZ, P]
     for name in ("fr_ctx_create", "fr_workspace_bytes", "fr_workspace_init", "fr_workspace_bytes_plain", "fr_step",
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
                  "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics",
-                 "fr_solve_progress"):
+                 "fr_solve_progress", "fr_grad_converged"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -212,9 +217,11 @@ def _f32(t: torch.Tensor, shape, name):
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {tuple(shape)}")
 
 
-def _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol=0.0) -> _Optim:
+def _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol=0.0, sinkhorn_tol=0.0,
+           cg_iters=0) -> _Optim:
     return _Optim(FR_ADAM if rule == "adam" else FR_GD, float(lr), float(beta1), float(beta2),
-                  float(adam_eps), int(N), int(K), float(grad_tol))
+                  float(adam_eps), int(N), int(K), float(grad_tol), float(sinkhorn_tol),
+                  int(cg_iters))
 
 
 def workspace_bytes(prob: Problem, K: int = 1) -> int:
@@ -319,7 +326,7 @@ def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF
 
 
 def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, start_step, K,
-           want_X, x_dtype, plain, grad_tol=0.0):
+           want_X, x_dtype, plain, grad_tol=0.0, sinkhorn_tol=0.0, cg_iters=0):
     U, I, m = prob.U, prob.I, prob.m
     dev = ctx.device
     C = torch.zeros((U, I, m), dtype=torch.float32, device=dev) if C0 is None else C0.clone()
@@ -334,7 +341,7 @@ def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, sta
         X = torch.empty((U, I, m), dtype=torch.bfloat16 if x_dtype == "bf16" else torch.float32,
                         device=dev)
     Fh = torch.empty(N + 1, dtype=torch.float64, device=dev)
-    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol)
+    o = _optim(rule, lr, beta1, beta2, adam_eps, N, K, grad_tol, sinkhorn_tol, cg_iters)
     p = prob.c()
     n = ctypes.c_size_t()
     if plain:
@@ -347,22 +354,51 @@ def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, sta
     _check(fn(ctx.handle, ctypes.byref(p), ctypes.byref(o), _ptr(C), _ptr(mom), _ptr(vel),
               int(start_step), _ptr(X), FR_BF16 if x_dtype == "bf16" else FR_F32, _ptr(Fh),
               _ptr(ws), ws.numel(), _stream(dev)), "fr_solve_plain" if plain else "fr_solve")
-    steps, gn = ctypes.c_int64(), ctypes.c_double()
+    steps, gn, sk = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
     _check(load().fr_solve_progress(ctx.handle, _ptr(ws), _stream(dev), ctypes.byref(steps),
-                                    ctypes.byref(gn)), "fr_solve_progress")
+                                    ctypes.byref(gn), ctypes.byref(sk)), "fr_solve_progress")
     return {"C": C, "X": X, "F_hist": Fh, "mom": mom, "vel": vel,
-            "updates": int(steps.value) - int(start_step), "last_gnorm": float(gn.value)}
+            "updates": int(steps.value) - int(start_step), "last_gnorm": float(gn.value),
+            "sinkhorn_iters": int(sk.value)}
 
 
 def solve(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,
           beta2: float = 0.999, adam_eps: float = 1e-8, C0=None, mom=None, vel=None,
           start_step: int = 0, K: int = 0, want_X: bool = True, x_dtype: str = "f32",
-          grad_tol: float = 0.0):
+          grad_tol: float = 0.0, sinkhorn_tol: float = 0.0, cg_iters: int = 0):
     """fr_solve: Algorithm 1 with at most N ascent steps (captured as a HIP
-    graph); grad_tol = t > 0 ends the loop at the first ||dF/dC||_F <= t.
-    The result's "updates" counts the updates applied."""
+    graph); grad_tol = t > 0 ends the loop at the first ||dF/dC||_F <= t;
+    sinkhorn_tol > 0 selects the converged-map form (warm starts, tolerance,
+    implicit gradients).  The result's "updates" counts the updates applied,
+    "sinkhorn_iters" the Sinkhorn iterations of the converged-map form."""
     return _solve(load().fr_solve, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel,
-                  start_step, K, want_X, x_dtype, False, grad_tol)
+                  start_step, K, want_X, x_dtype, False, grad_tol, sinkhorn_tol, cg_iters)
+
+
+def grad_converged(ctx: Context, prob: Problem, C: torch.Tensor, sinkhorn_tol: float,
+                   gF: float = 1.0, cg_iters: int = 0, want_dr: bool = True, sync: bool = True):
+    """fr_grad_converged: Imp and F of the converged plan of C and gF * dF/dC
+    (and dF/dr) by the implicit function theorem."""
+    U, I, m = prob.U, prob.I, prob.m
+    _f32(C, (U, I, m), "C")
+    imp = torch.empty(I, dtype=torch.float64, device=C.device)
+    F = torch.empty(1, dtype=torch.float64, device=C.device)
+    dC = torch.empty_like(C)
+    dr = torch.empty((U, I), dtype=torch.float32, device=C.device) if want_dr else None
+    n = ctypes.c_size_t()
+    o = _optim("adam", 0.0, 0.9, 0.999, 1e-8, 0, 1, 0.0, sinkhorn_tol)
+    p = prob.c()
+    _check(load().fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)),
+           "fr_workspace_bytes")
+    ws = ctx.workspace(n.value)
+    _check(load().fr_grad_converged(ctx.handle, ctypes.byref(p), _ptr(C), float(sinkhorn_tol),
+                                    int(cg_iters), float(gF), _ptr(imp), _ptr(F), _ptr(dC),
+                                    _ptr(dr), _ptr(ws), ws.numel(), _stream(C.device)),
+           "fr_grad_converged")
+    if sync:
+        _check(load().fr_sync_status(ctx.handle, _ptr(ws), _stream(C.device)),
+               "fr_grad_converged (device)")
+    return {"imp": imp, "F": F, "dC": dC, "dr": dr}
 
 
 def solve_plain(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam",

@@ -184,14 +184,15 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t hdr, imp, partial, y, hist, grad, gpart, total;
+    size_t hdr, imp, partial, y, hist, grad, gpart, gw, phi, total;
     int nchunk, nck, hs;
 };
 
 int n_checkpoints(int T, int K) { return (T + K - 1) / K + 1; }
 
-// tol: room for the gradient and its norm partials (gradient-norm stop).
-Layout layout(const fr_problem* p, int K, bool tol = false) {
+// tol: room for the gradient and its norm partials (gradient-norm stop);
+// conv: the converged-map form's potentials.
+Layout layout(const fr_problem* p, int K, bool tol = false, bool conv = false) {
     Layout L;
     const int64_t U = p->n_users;
     const int I = p->n_items;
@@ -216,6 +217,13 @@ Layout layout(const fr_problem* p, int K, bool tol = false) {
         off += align_up(sizeof(float) * (size_t)n);
         L.gpart = off;
         off += align_up(sizeof(double) * (size_t)gnorm_blocks(n));
+    }
+    L.gw = L.phi = off;
+    if (conv) {
+        L.gw = off;
+        off += align_up(sizeof(float) * (size_t)U * L.hs);
+        L.phi = off;
+        off += align_up(sizeof(float) * (size_t)U * I);
     }
     L.total = off;
     return L;
@@ -273,6 +281,8 @@ fr_status check_optim(const fr_optim* o, const float* mom, const float* vel, int
          !(o->adam_eps >= 0.f)))
         return FR_E_PARAM;
     if (!(o->grad_tol >= 0.0) || !isfinite(o->grad_tol)) return FR_E_PARAM;
+    if (!(o->sinkhorn_tol >= 0.f) || !isfinite(o->sinkhorn_tol) || o->cg_iters < 0)
+        return FR_E_PARAM;
     return FR_OK;
 }
 
@@ -340,8 +350,20 @@ __global__ void k_init_header(WsHeader* h, int64_t step) {
         h->F = 0.0;
         h->rep = 0;
         h->gnorm = 0.0;
+        h->sk_iters = 0;
     }
 }
+
+// Column potentials of the converged-map form before its first forward:
+// 0 on the real columns, the padding value on the padded ones.
+__global__ void k_warm_init(float* gw, int64_t U, int m, int hs) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= U * hs) return;
+    gw[j] = ((int)(j % hs) < m) ? 0.f : -1.0e30f;
+}
+
+int cg_cap(int m, int requested) { return requested > 0 ? requested : 2 * m + 8; }
+constexpr float kCgTol = 1e-6f;
 
 __global__ void k_set_step(WsHeader* h, int64_t step) {
     if (threadIdx.x == 0 && blockIdx.x == 0) h->step = step;
@@ -581,8 +603,13 @@ fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size
     if (!out) return FR_E_NULL;
     fr_status st = check_problem(prob);
     if (st) return st;
+    if (optim && (!(optim->grad_tol >= 0.0) || !isfinite(optim->grad_tol) ||
+                  !(optim->sinkhorn_tol >= 0.f) || !isfinite(optim->sinkhorn_tol) ||
+                  optim->cg_iters < 0))
+        return FR_E_PARAM;
     const int K = optim ? resolve_k(optim->checkpoint_every) : 1;
-    *out = layout(prob, K, optim && optim->grad_tol > 0.0).total;
+    *out = layout(prob, K, optim && optim->grad_tol > 0.0, optim && optim->sinkhorn_tol > 0.f)
+               .total;
     return FR_OK;
 }
 
@@ -776,7 +803,8 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
     const int K = resolve_k(optim->checkpoint_every);
     const bool tol = optim->grad_tol > 0.0;
-    const Layout Lw = layout(prob, K, tol);
+    const bool conv = optim->sinkhorn_tol > 0.f;
+    const Layout Lw = layout(prob, K, tol, conv);
     if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
     Shape sh;
     if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, K, &sh))) return st;
@@ -821,11 +849,30 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         b.Cw = nullptr;
         b.dC = (float*)(w + Lw.grad);
     }
+    if (conv) {
+        // converged-map form: warm-started forward to tolerance, implicit gradient
+        float* gw = (float*)(w + Lw.gw);
+        const int64_t ng = prob->n_users * (int64_t)Lw.hs;
+        hipLaunchKernelGGL(k_warm_init, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, gw,
+                           prob->n_users, prob->m, Lw.hs);
+        a.hist = nullptr;
+        a.gw = gw;
+        a.phi = (float*)(w + Lw.phi);
+        a.tol = optim->sinkhorn_tol;
+        a.iters = &hdr->sk_iters;
+        b.gw = gw;
+        b.phi = a.phi;
+        b.cg_max = cg_cap(prob->m, optim->cg_iters);
+        b.cg_tol = kCgTol;
+    }
     auto outer_step = [&]() {
-        sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+        (conv ? sh.fe->fwdc : sh.fe->fwd)(a, sh.grid, sh.block, sh.lds_fwd, s);
         launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
                       start_step, hdr, tol ? ADV_REP : ADV_REP_STEP, s);
-        sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+        if (conv)
+            sh.fe->ibwd(b, sh.grid, sh.block, sh.lds_fwd, s);
+        else
+            sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
         if (tol)
             launch_gnorm_update(b.dC, C, adam_m, adam_v, ncell, optim->rule, optim->lr,
                                 optim->beta1, optim->beta2, optim->adam_eps,
@@ -833,7 +880,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     };
 
     const int N = optim->outer_steps;
-    if (N > 0 && ctx->timing && !tol) {
+    if (N > 0 && ctx->timing && !tol && !conv) {
         // direct launches, each fused kernel bracketed by events
         std::vector<hipEvent_t> ev(4 * (size_t)N);
         for (auto& x : ev) FR_TRY(hipEventCreate(&x));
@@ -881,7 +928,12 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     a.stop = nullptr;
     a.X = X_out;
     a.x_bf16 = (x_dtype == FR_BF16);
-    if ((st = launch_fwd(sh, a, s))) return st;
+    if (conv) {
+        sh.fe->fwdc(a, sh.grid, sh.block, sh.lds_fwd, s);
+        FR_TRY(hipGetLastError());
+    } else if ((st = launch_fwd(sh, a, s))) {
+        return st;
+    }
     launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
                   start_step, hdr, ADV_NONE, s);
     FR_TRY(hipGetLastError());
@@ -889,7 +941,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
 }
 
 fr_status fr_solve_progress(fr_ctx* ctx, void* ws, void* stream, int64_t* steps,
-                            double* last_gnorm) {
+                            double* last_gnorm, int64_t* sinkhorn_iters) {
     if (!ctx || !ws) return FR_E_NULL;
     FR_TRY(hipSetDevice(ctx->device));
     hipStream_t s = pick_stream(ctx, stream);
@@ -898,6 +950,53 @@ fr_status fr_solve_progress(fr_ctx* ctx, void* ws, void* stream, int64_t* steps,
     FR_TRY(hipMemcpy(&h, ws, sizeof(WsHeader), hipMemcpyDeviceToHost));
     if (steps) *steps = h.step;
     if (last_gnorm) *last_gnorm = h.gnorm;
+    if (sinkhorn_iters) *sinkhorn_iters = h.sk_iters;
+    return FR_OK;
+}
+
+fr_status fr_grad_converged(fr_ctx* ctx, const fr_problem* prob, const float* C,
+                            float sinkhorn_tol, int32_t cg_iters, double gF, double* imp_out,
+                            double* F, float* dC, float* dr, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !dC || !ws) return FR_E_NULL;
+    if (!(sinkhorn_tol > 0.f) || !isfinite(sinkhorn_tol) || cg_iters < 0 || !isfinite(gF))
+        return FR_E_PARAM;
+    const Layout Lw = layout(prob, 1, false, true);
+    if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
+    Shape sh;
+    if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, 1, &sh))) return st;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    char* w = (char*)ws;
+    WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
+    double* imp = imp_out ? imp_out : (double*)(w + Lw.imp);
+    float* gw = (float*)(w + Lw.gw);
+    const int64_t ng = prob->n_users * (int64_t)Lw.hs;
+    hipLaunchKernelGGL(k_warm_init, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, gw,
+                       prob->n_users, prob->m, Lw.hs);
+    FwdArgs a = fwd_args(prob, sh, C);
+    a.y = (float*)(w + Lw.y);
+    a.gw = gw;
+    a.phi = (float*)(w + Lw.phi);
+    a.tol = sinkhorn_tol;
+    a.iters = &hdr->sk_iters;
+    sh.fe->fwdc(a, sh.grid, sh.block, sh.lds_fwd, s);
+    launch_impact(a.y, prob->n_users, prob->n_items, (double*)(w + Lw.partial), Lw.nchunk, imp, F,
+                  nullptr, 0, hdr, ADV_NONE, s);
+    BwdArgs b = bwd_args(prob, sh, C);
+    b.imp = imp;
+    b.gF = gF;
+    b.dC = dC;
+    b.dr = dr;
+    b.gw = gw;
+    b.phi = a.phi;
+    b.cg_max = cg_cap(prob->m, cg_iters);
+    b.cg_tol = kCgTol;
+    sh.fe->ibwd(b, sh.grid, sh.block, sh.lds_fwd, s);
+    FR_TRY(hipGetLastError());
     return FR_OK;
 }
 
@@ -945,6 +1044,7 @@ fr_status fr_solve_plain(fr_ctx* ctx, const fr_problem* prob, const fr_optim* op
     if ((st = check_optim(optim, adam_m, adam_v, start_step))) return st;
     if (!C || !F_hist || !ws) return FR_E_NULL;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    if (optim->sinkhorn_tol > 0.f) return FR_E_UNSUPPORTED;   // fused form only
     const PlainLayout Lw = plain_layout(prob);
     if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
     FR_TRY(hipSetDevice(ctx->device));
@@ -1012,7 +1112,7 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     if (!ctx || !optim || !probs || !C || !F_hist || !ws) return FR_E_NULL;
     // the gradient-norm test of Algorithm 1 is per instance: not offered for
     // the batched solve
-    if (optim->grad_tol != 0.0) return FR_E_UNSUPPORTED;
+    if (optim->grad_tol != 0.0 || optim->sinkhorn_tol != 0.f) return FR_E_UNSUPPORTED;
     if (n_inst < 1) return FR_E_SHAPE;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
     for (int j = 0; j < n_inst; ++j) {

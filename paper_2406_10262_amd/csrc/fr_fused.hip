@@ -444,35 +444,45 @@ __device__ __forceinline__ void row_pass_recomp(float (&c)[R][MP], const float (
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Column half-step: gamma_k += log2 b_k - log2 sig_k.
-template <int MP>
-__device__ __forceinline__ void col_update(float (&acc)[MP], float (&gam)[MP],
-                                           const Cols<MP, false>& cs, int m, const Team& tm) {
+// Column half-step: gamma_k += log2 b_k - log2 sig_k.  With CHECK, returns
+// whether no potential moved by more than tol (the team-uniform convergence
+// test of the warm-started form).
+template <int MP, bool CHECK>
+__device__ __forceinline__ bool col_update(float (&acc)[MP], float (&gam)[MP],
+                                           const Cols<MP, false>& cs, const Team& tm, float tol) {
     group_allreduce<MP>(acc, tm.L);
+    float dmax = 0.f;
 #pragma unroll
-    for (int k = 0; k < MP; ++k) gam[k] += cs.lb[k] - lg2(fmaxf(acc[k], kTiny));
-    (void)m;
+    for (int k = 0; k < MP; ++k) {
+        const float d = cs.lb[k] - lg2(fmaxf(acc[k], kTiny));
+        if (CHECK && gam[k] > 0.5f * kNeg) dmax = fmaxf(dmax, fabsf(d));   // real columns
+        gam[k] += d;
+    }
+    return dmax <= tol;
 }
 
-template <int MP>
-__device__ __forceinline__ void col_update_wide(float (&q)[n_slots(MP)], float (&gam)[MP],
+template <int MP, bool CHECK>
+__device__ __forceinline__ bool col_update_wide(float (&q)[n_slots(MP)], float (&gam)[MP],
                                                 Cols<MP, true>& cs, const Team& tm, float* red,
-                                                int par) {
+                                                int par, float tol) {
     const float tot = wide_total<MP>(q, tm, cs.col, red, par);
-    if (cs.live) cs.gd += cs.lbc - lg2(tot);
+    const float d = cs.lbc - lg2(tot);
+    if (cs.live) cs.gd += d;
     spread_owned<MP>(cs.gd, gam);
+    return CHECK ? !wave_any(cs.live && fabsf(d) > tol) : true;
 }
 
 // One forward Sinkhorn iteration of a team.
-template <int MP, int R, bool WIDE, bool RECOMP, bool SHIFT = false>
-__device__ __forceinline__ void fwd_iter(float (&c)[R][MP], const float (&om)[R],
+template <int MP, int R, bool WIDE, bool RECOMP, bool SHIFT = false, bool CHECK = false>
+__device__ __forceinline__ bool fwd_iter(float (&c)[R][MP], const float (&om)[R],
                                          float (&gam)[MP], float (&S)[R], float (&off)[R],
                                          Cols<MP, WIDE>& cs, int m, const Team& tm, float* red,
-                                         int par) {
+                                         int par, float tol = 0.f) {
+    (void)m;
     if constexpr (!WIDE) {
         float acc[MP];
         row_pass<MP, R>(c, om, gam, acc, S, off);
-        col_update<MP>(acc, gam, cs, m, tm);
+        return col_update<MP, CHECK>(acc, gam, cs, tm, tol);
     } else {
         float q[n_slots(MP)];
         if constexpr (RECOMP) {
@@ -482,7 +492,7 @@ __device__ __forceinline__ void fwd_iter(float (&c)[R][MP], const float (&om)[R]
             row_pass<MP, R>(c, om, gam, acc, S, off);
             scatter_all<MP>(acc, q);
         }
-        col_update_wide<MP>(q, gam, cs, tm, red, par);
+        return col_update_wide<MP, CHECK>(q, gam, cs, tm, red, par, tol);
     }
 }
 
@@ -515,7 +525,7 @@ __device__ __forceinline__ void load_costs(const float* C, int64_t u, bool activ
 // ---------------------------------------------------------------------------
 // Forward for the teams of one block: team q of the block owns consumer
 // u_first + q.
-template <int MP, int R, bool WIDE, bool RECOMP>
+template <int MP, int R, bool WIDE, bool RECOMP, bool CONV = false>
 __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int64_t u = u_first + tm.team;
@@ -530,21 +540,48 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
     float gam[MP];
     Cols<MP, WIDE> cs;
     cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gam);
+    if (CONV && a.gw) {   // warm start from the previous potentials
+        const float* gs = a.gw + (active ? u : 0) * (int64_t)a.hs;
+        if constexpr (WIDE) {
+            cs.gd = (active && cs.col >= 0) ? gs[cs.col] : cs.gd;
+            spread_owned<MP>(cs.gd, gam);
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) gam[k] = active ? gs[k] : gam[k];
+        }
+    }
     float* hist = (a.hist != nullptr && active) ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
     if (hist) put_gamma<MP, WIDE>(hist, gam, cs, tm);
 
     float S[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) S[j] = 0.f;
-    for (int t = 1; t <= a.T; ++t) {
-        fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, S, off, cs, m, tm, red, t & 1);
-        if (hist) {
-            if (t % a.K == 0)
-                put_gamma<MP, WIDE>(hist + (int64_t)(t / a.K) * a.hs, gam, cs, tm);
-            else if (t == a.T)
-                put_gamma<MP, WIDE>(hist + (int64_t)(a.nck - 1) * a.hs, gam, cs, tm);
+    int used = a.T;
+    if constexpr (CONV) {
+        // converged-map form: stop once no potential moves by more than tol
+        for (int t = 1; t <= a.T; ++t) {
+            if (fwd_iter<MP, R, WIDE, RECOMP, false, true>(c, om, gam, S, off, cs, m, tm, red,
+                                                           t & 1, a.tol)) {
+                used = t;
+                break;
+            }
+        }
+    } else {
+        for (int t = 1; t <= a.T; ++t) {
+            fwd_iter<MP, R, WIDE, RECOMP>(c, om, gam, S, off, cs, m, tm, red, t & 1);
+            if (hist) {
+                if (t % a.K == 0)
+                    put_gamma<MP, WIDE>(hist + (int64_t)(t / a.K) * a.hs, gam, cs, tm);
+                else if (t == a.T)
+                    put_gamma<MP, WIDE>(hist + (int64_t)(a.nck - 1) * a.hs, gam, cs, tm);
+            }
         }
     }
+    if (CONV && active) {
+        if (a.gw) put_gamma<MP, WIDE>(a.gw + u * (int64_t)a.hs, gam, cs, tm);
+        if (a.iters && tm.lt == 0) atomicAdd((unsigned long long*)a.iters, (unsigned long long)used);
+    }
+    (void)used;
 
     const int mo = opaque_u(m);
     float ek[MP];
@@ -580,6 +617,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
         }
         if (a.y) a.y[row] = a.r[row] * yy;
         if (a.pot) a.pot[u * (int64_t)(I + m) + i] = (phi - off[j]) * a.eps_ln2;
+        if (a.phi) a.phi[row] = phi - off[j];
     }
     if (a.pot && active && tm.lt == 0) {
 #pragma unroll
@@ -880,6 +918,274 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
 }
 
 // ---------------------------------------------------------------------------
+// Implicit-function gradient at a converged plan (the converged-map form of
+// Algorithm 1).  With the plan X, G_ik = gF r_i e_k / Imp_i (0 on the dummy),
+// the row and column sums rX, cX of X and h_i = sum_k X_ik G_ik, the gradient
+// of the balanced plan is
+//   dF/dc_ik = -(1/eps) X_ik (G_ik - lam_i - mu_k),
+// where mu (mu_{m-1} = 0) solves the Schur system of the optimality
+// conditions,
+//   S mu = t,  S = diag(cX) - X^T diag(rX)^-1 X,  t_k = sum_i X_ik (G_ik - h_i / rX_i),
+// and lam_i = (h_i - sum_k X_ik mu_k) / rX_i.  On mu_{m-1} = 0, S is symmetric
+// positive definite (v^T S v is a sum of per-row variances of v), so mu comes
+// from conjugate gradients preconditioned by diag(S): one product S p per
+// iteration is two FMAs per plan cell and one column reduction.
+
+// Column vectors of the solver: every lane holds all of them in a narrow
+// team; in a wide team each lane holds the component of the column it owns.
+template <int MP, bool WIDE>
+struct CVec;
+template <int MP>
+struct CVec<MP, false> {
+    float v[MP];
+};
+template <int MP>
+struct CVec<MP, true> {
+    float v;
+};
+
+template <int MP, bool WIDE>
+struct Solver {
+    const Team& tm;
+    Cols<MP, WIDE>& cs;
+    float* red;
+    int par = 0;
+    CVec<MP, WIDE> msk;   // 1 on the real positions k < m - 1, else 0
+
+    __device__ Solver(const Team& t, Cols<MP, WIDE>& c, float* r, int m) : tm(t), cs(c), red(r) {
+        if constexpr (WIDE) {
+            msk.v = (cs.col >= 0 && cs.col < m - 1) ? 1.f : 0.f;
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) msk.v[k] = (k < m - 1) ? 1.f : 0.f;
+        }
+    }
+    // team sums of the lanes' column partials
+    __device__ CVec<MP, WIDE> reduce(float (&acc)[MP]) {
+        CVec<MP, WIDE> out;
+        if constexpr (WIDE) {
+            float q[n_slots(MP)];
+            scatter_all<MP>(acc, q);
+            out.v = wide_total<MP>(q, tm, cs.col, red, par);
+            par ^= 1;
+        } else {
+            group_allreduce<MP>(acc, tm.L);
+#pragma unroll
+            for (int k = 0; k < MP; ++k) out.v[k] = acc[k];
+        }
+        return out;
+    }
+    __device__ float dot(const CVec<MP, WIDE>& x, const CVec<MP, WIDE>& y) {
+        if constexpr (WIDE) {
+            float t[1] = {x.v * y.v * msk.v};
+            group_allreduce<1>(t, 64);
+            return t[0];
+        } else {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) s = fmaf(x.v[k] * msk.v[k], y.v[k], s);
+            return s;
+        }
+    }
+    // the vector as a uniform array (scalars in a wide team)
+    __device__ void spread(const CVec<MP, WIDE>& x, float (&out)[MP]) {
+        if constexpr (WIDE) {
+            spread_owned<MP>(x.v * msk.v, out);
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) out[k] = x.v[k] * msk.v[k];
+        }
+    }
+};
+
+template <int MP, bool WIDE, class F>
+__device__ __forceinline__ void cv_apply(CVec<MP, WIDE>& out, F&& f) {
+    if constexpr (WIDE) {
+        out.v = f(out.v, 0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < MP; ++k) out.v[k] = f(out.v[k], k);
+    }
+}
+
+template <int MP, int R, bool WIDE>
+__device__ __forceinline__ void ibwd_body(const BwdArgs& a, int64_t u_first, float* smem) {
+    const Team tm = make_team(a.L);
+    const int teams = blockDim.x / a.L;
+    const int64_t u = u_first + tm.team;
+    const bool active = tm.team < teams && u < a.U;
+    const int I = a.I, m = a.m;
+    float* red = smem + tm.team * (2 * tm.W * MP);
+
+    float x[R][MP], om[R], off[R];
+    load_costs<MP, R>(a.C, u, active, tm, I, m, a.c2, x, om, off);
+    float gam[MP];
+    Cols<MP, WIDE> cs;
+    cs.init(tm, m, 0.f, 1.f, gam);
+    const float* gs = a.gw + (active ? u : 0) * (int64_t)a.hs;
+    if constexpr (WIDE) {
+        cs.gd = (active && cs.col >= 0) ? gs[cs.col] : kNeg;
+        spread_owned<MP>(cs.gd, gam);
+    } else {
+#pragma unroll
+        for (int k = 0; k < MP; ++k) gam[k] = active ? gs[k] : kNeg;
+    }
+
+    // the plan, its row sums, h_i and the column partials of cX, t and diag S
+    const int mo = opaque_u(m);
+    float ek[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) ek[k] = (k < mo - 1) ? a.e[k] : 0.f;
+    float rX[R], h[R], rg[R];
+    float ac[MP], at[MP], ad[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) ac[k] = at[k] = ad[k] = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        const bool valid = active && i < I;
+        const float ph = valid ? a.phi[u * I + i] + off[j] : 0.f;
+        rg[j] = valid ? (float)(a.gF * (double)a.r[u * I + i] / a.imp[i]) : 0.f;
+        float s = 0.f, hh = 0.f;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            const float xv = valid ? ex2((x[j][k] + gam[k]) + ph) : 0.f;
+            x[j][k] = xv;
+            s += xv;
+            hh = fmaf(ek[k], xv, hh);
+        }
+        rX[j] = valid ? s : 1.f;
+        h[j] = rg[j] * hh;
+        const float ir = 1.f / rX[j];
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            ac[k] += x[j][k];
+            at[k] = fmaf(x[j][k], rg[j] * ek[k] - h[j] * ir, at[k]);
+            ad[k] = fmaf(x[j][k] * x[j][k], ir, ad[k]);
+        }
+    }
+    Solver<MP, WIDE> sv(tm, cs, red, m);
+    const CVec<MP, WIDE> cX = sv.reduce(ac);
+    const CVec<MP, WIDE> tv = sv.reduce(at);
+    CVec<MP, WIDE> dg = sv.reduce(ad);
+    cv_apply<MP, WIDE>(dg, [&](float d, int k) {
+        float cxk;
+        if constexpr (WIDE) cxk = cX.v; else cxk = cX.v[k];
+        const float v = cxk - d;
+        return v > 0.f ? v : 1.f;
+    });
+
+    // preconditioned conjugate gradients for mu
+    CVec<MP, WIDE> xs, rr = tv, z, p, Sp;
+    cv_apply<MP, WIDE>(xs, [](float, int) { return 0.f; });
+    auto precond = [&](const CVec<MP, WIDE>& r) {
+        CVec<MP, WIDE> o;
+        if constexpr (WIDE) {
+            o.v = r.v / dg.v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) o.v[k] = r.v[k] / dg.v[k];
+        }
+        return o;
+    };
+    z = precond(rr);
+    p = z;
+    float rz = sv.dot(rr, z);
+    const float tn = sqrtf(sv.dot(tv, tv));
+    for (int it = 0; it < a.cg_max && tn > 0.f; ++it) {
+        float pa[MP];
+        sv.spread(p, pa);
+        float acc[MP];
+#pragma unroll
+        for (int k = 0; k < MP; ++k) acc[k] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) s = fmaf(x[j][k], pa[k], s);
+            const float w = s / rX[j];
+#pragma unroll
+            for (int k = 0; k < MP; ++k) acc[k] = fmaf(x[j][k], w, acc[k]);
+        }
+        const CVec<MP, WIDE> tot = sv.reduce(acc);
+        if constexpr (WIDE) {
+            Sp.v = cX.v * p.v - tot.v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) Sp.v[k] = cX.v[k] * p.v[k] - tot.v[k];
+        }
+        const float pSp = sv.dot(p, Sp);
+        if (!(pSp > 0.f)) break;
+        const float al = rz / pSp;
+        if constexpr (WIDE) {
+            xs.v = fmaf(al, p.v, xs.v);
+            rr.v = fmaf(-al, Sp.v, rr.v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                xs.v[k] = fmaf(al, p.v[k], xs.v[k]);
+                rr.v[k] = fmaf(-al, Sp.v[k], rr.v[k]);
+            }
+        }
+        if (sqrtf(sv.dot(rr, rr)) <= a.cg_tol * tn) break;
+        z = precond(rr);
+        const float rzn = sv.dot(rr, z);
+        const float be = rzn / rz;
+        rz = rzn;
+        if constexpr (WIDE) {
+            p.v = fmaf(be, p.v, z.v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) p.v[k] = fmaf(be, p.v[k], z.v[k]);
+        }
+    }
+    float mu[MP];
+    sv.spread(xs, mu);
+
+    // lam, the gradient, and the update (or dF/dC)
+    if (!active) return;
+    float bc1 = 1.f, bc2 = 1.f;
+    if (a.Cw && a.rule == 0) {
+        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
+        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
+        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        if (i >= I) continue;
+        float xm = 0.f, xe = 0.f;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            xm = fmaf(x[j][k], mu[k], xm);
+            xe = fmaf(ek[k], x[j][k], xe);
+        }
+        const float lam = (h[j] - xm) / rX[j];
+        if (a.dr) a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * xe;
+        const int64_t base = (u * I + i) * (int64_t)m;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            if (k >= mo) continue;
+            const float g = -a.inv_eps * x[j][k] * (rg[j] * ek[k] - lam - mu[k]);
+            if (a.dC) a.dC[base + k] = g;
+            if (a.Cw) {
+                const float craw = a.C[base + k];
+                if (a.rule == 0) {
+                    const float gl = -g;
+                    const float mo1 = a.b1 * a.mom[base + k] + (1.f - a.b1) * gl;
+                    const float ve = a.b2 * a.vel[base + k] + (1.f - a.b2) * gl * gl;
+                    a.mom[base + k] = mo1;
+                    a.vel[base + k] = ve;
+                    a.Cw[base + k] = craw - a.lr * (mo1 / bc1) / (sqrtf(ve / bc2) + a.aeps);
+                } else {
+                    a.Cw[base + k] = craw + a.lr * g;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-lane registers available at launch bound LB (512 per SIMD lane shared
 // by LB / 256 waves, at most 256 architectural VGPRs), minus a reserve for
 // addresses and temporaries.
@@ -897,12 +1203,28 @@ __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
                                                      smem);
 }
 
+// Converged-map forward: warm start from a.gw, stop at tolerance a.tol.
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_fwdc(FwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;
+    fwd_body<MP, R, WIDE, recomp_fwd<R, LB, WIDE>(), true>(
+        a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+}
+
 template <int MP, int R, int LB, bool WIDE>
 __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
     extern __shared__ float smem[];
     if (a.stop && *a.stop) return;   // the outer loop has ended
     bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
                                                      smem);
+}
+
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_ibwd(BwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    ibwd_body<MP, R, WIDE>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,6 +1302,14 @@ template <int MP, int R, int LB, bool WIDE>
 void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_bwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
+template <int MP, int R, int LB, bool WIDE>
+void launch_fwdc(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwdc<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
+}
+template <int MP, int R, int LB, bool WIDE>
+void launch_ibwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_ibwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
+}
 
 template <int R, int LB, bool WIDE>
 constexpr FusedEntry entry() {
@@ -992,14 +1322,17 @@ constexpr FusedEntry entry() {
                           recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>,
                           &launch_bwd<FR_MP, R, LB, WIDE>,
+                          &launch_fwdc<FR_MP, R, LB, WIDE>,
+                          &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_bfwd<FR_MP, R, WIDE>,
                           &launch_bbwd<FR_MP, R, WIDE>,
                           &occupancy_bfwd<FR_MP, R, WIDE>,
                           &occupancy_bbwd<FR_MP, R, WIDE>};
     } else {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
-                          &launch_fwd<FR_MP, R, LB, WIDE>,
-                          &launch_bwd<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr};
+                          &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,
+                          &launch_fwdc<FR_MP, R, LB, WIDE>, &launch_ibwd<FR_MP, R, LB, WIDE>,
+                          nullptr, nullptr, nullptr, nullptr};
     }
 }
 

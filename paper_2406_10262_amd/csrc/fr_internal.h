@@ -18,6 +18,7 @@ struct WsHeader {
     double F;             // last objective value
     int64_t rep;          // outer steps recorded in the F history since the start
     double gnorm;         // ||dF/dC||_F of the last gradient tested
+    int64_t sk_iters;     // Sinkhorn iterations used, summed over consumers and forwards
 };
 
 // ---------------------------------------------------------------------------
@@ -32,6 +33,10 @@ struct FwdArgs {
     void* X;               // [U][I][m] plan (or null)
     float* pot;            // [U][I+m] potentials in cost units (or null)
     const int32_t* stop;   // skip the launch when *stop != 0 (or null)
+    float* gw;             // [U][hs] base-2 column potentials: start (warm) and result, or null
+    float* phi;            // [U][I] base-2 row potentials of the uncentred costs (or null)
+    int64_t* iters;        // sum of the iterations used, added per consumer (or null)
+    float tol;             // > 0: stop a consumer once no potential moves by more than tol
     int64_t U;
     int I, m, T, K, nck, hs, L, x_bf16;
     float c2;              // -1 / (eps ln 2): exponent scale of a cost
@@ -51,6 +56,10 @@ struct BwdArgs {
     float* vel;            // Adam second moment (or null)
     const int64_t* step_ptr;  // device Adam step counter (or null: use step_const)
     const int32_t* stop;      // skip the launch when *stop != 0 (or null)
+    const float* gw;          // implicit form: converged column potentials [U][hs]
+    const float* phi;         // implicit form: row potentials [U][I]
+    int cg_max;               // implicit form: conjugate-gradient iteration cap
+    float cg_tol;             // implicit form: relative residual to stop at
     int64_t step_const;
     double gF;
     int64_t U;
@@ -80,6 +89,8 @@ struct FusedEntry {
     bool recomp_b;      // backward likewise
     FwdLaunch fwd;
     BwdLaunch bwd;
+    FwdLaunch fwdc;     // converged-map forward (warm start, tolerance)
+    BwdLaunch ibwd;     // implicit-function gradient at a converged plan
     BFwdLaunch bfwd;    // persistent batched forms (launch bound 256 only)
     BBwdLaunch bbwd;
     Occupancy occ_bfwd;

@@ -141,4 +141,20 @@ def test_gradient_norm_stop_needs_gradient_room(lib):
     o.grad_tol = 1e-3
     assert lib.fr_workspace_bytes(ctypes.byref(_prob(fr)), ctypes.byref(o), ctypes.byref(n1)) == 0
     assert n1.value >= n0.value + 10 * 20 * 5 * 4
-    assert lib.fr_solve_progress(None, 1, None, None, None) == 1
+    assert lib.fr_solve_progress(None, 1, None, None, None, None) == 1
+
+
+def test_converged_map_form_validation(lib):
+    import paper_2406_10262_amd as fr
+    p = _prob(fr)
+    n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+    o = fr._Optim(0, 0.01, 0.9, 0.999, 1e-8, 5, 1)
+    assert lib.fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n0)) == 0
+    o.sinkhorn_tol = 1e-4
+    assert lib.fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n1)) == 0
+    assert n1.value >= n0.value + 10 * 8 * 4        # warm-start potentials per consumer
+    for tol, cg in ((float("nan"), 0), (float("inf"), 0), (-1e-3, 0), (1e-3, -1)):
+        o.sinkhorn_tol, o.cg_iters = tol, cg
+        assert lib.fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n1)) == 3
+    assert lib.fr_grad_converged(None, ctypes.byref(p), 1, 1e-4, 0, 1.0, None, None, 1, None, 1,
+                                 10**9, None) == 1
