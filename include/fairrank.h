@@ -63,6 +63,7 @@ typedef enum {
 
 typedef enum { FR_F32 = 0, FR_BF16 = 1 } fr_dtype;   /* storage type of X     */
 typedef enum { FR_ADAM = 0, FR_GD = 1 } fr_rule;     /* ascent rule           */
+typedef enum { FR_FORM_LOG = 0, FR_FORM_SCALING = 1 } fr_form;  /* Sinkhorn form */
 
 typedef struct fr_ctx fr_ctx;
 
@@ -109,6 +110,23 @@ typedef struct {
 /* Creates a context bound to HIP device `device` (made current by every call). */
 fr_status fr_ctx_create(int device, fr_ctx** out);
 void fr_ctx_destroy(fr_ctx* ctx);
+
+/* Form of the fixed-T Sinkhorn forward that every later call on this context
+ * runs (fr_step, fr_solve, fr_autotune; the batched and plain solves and the
+ * backward's recomputation keep the log domain).  Both forms compute the same
+ * T iterates (Section 3's Sinkhorn iteration from g = 0); they differ in
+ * arithmetic only.
+ *   FR_FORM_LOG     (default) log-domain: one base-2 exponential per cell and
+ *                   iteration on centred scaled costs.
+ *   FR_FORM_SCALING matrix scaling u = 1/(K v), v = b/(K^T u) on a kernel
+ *                   K = 2^(a + gamma + phi) held in registers: two multiply-adds
+ *                   per cell and iteration, no exponential; the scalings are
+ *                   absorbed into the potentials (and K rebuilt from C, one
+ *                   exponential per cell) whenever a column scaling leaves
+ *                   [2^-32, 2^32], and also every absorb_every iterations if
+ *                   absorb_every > 0.
+ * FR_E_PARAM for an unknown form or absorb_every < 0.  Host only. */
+fr_status fr_ctx_set_form(fr_ctx* ctx, int32_t form, int32_t absorb_every);
 
 /* Bytes of workspace every call below needs for this problem (optim may be
  * NULL: then K = 1 and no Adam state; a positive grad_tol or sinkhorn_tol adds

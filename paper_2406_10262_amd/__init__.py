@@ -32,6 +32,7 @@ _lib = None
 FR_OK = 0
 FR_F32, FR_BF16 = 0, 1
 FR_ADAM, FR_GD = 0, 1
+FR_FORM_LOG, FR_FORM_SCALING = 0, 1
 STATUS = {
     0: "FR_OK", 1: "FR_E_NULL", 2: "FR_E_SHAPE", 3: "FR_E_PARAM", 4: "FR_E_WORKSPACE",
     5: "FR_E_DEVICE", 6: "FR_E_NONFINITE", 7: "FR_E_ZERO_IMPACT", 8: "FR_E_UNSUPPORTED",
@@ -94,6 +95,7 @@ def load():
     lib.fr_solve_batched.argtypes = [P, I32, PP, PO, P, P, P, I64, P, ctypes.c_int, P, P, SZ, P]
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
+    lib.fr_ctx_set_form.argtypes = [P, I32, I32]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.fr_workspace_bytes_metrics.argtypes = [PP, ctypes.POINTER(SZ)]
     lib.fr_solve_progress.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
@@ -105,7 +107,7 @@ def load():
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
                  "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics",
-                 "fr_solve_progress", "fr_grad_converged"):
+                 "fr_solve_progress", "fr_grad_converged", "fr_ctx_set_form"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -155,6 +157,12 @@ class Context:
                                             _stream(self.device)), "fr_workspace_init")
             self._ws = ws
         return self._ws
+
+    def set_form(self, form: str = "log", absorb_every: int = 0):
+        """fr_ctx_set_form: "log" (log-domain) or "scaling" (matrix scaling with
+        absorption) for the fixed-T forward of later calls."""
+        code = {"log": FR_FORM_LOG, "scaling": FR_FORM_SCALING}[form]
+        _check(load().fr_ctx_set_form(self.handle, code, int(absorb_every)), "fr_ctx_set_form")
 
     def set_launch(self, n_items: int, m: int, lanes: int, rows: int):
         _check(load().fr_set_launch(self.handle, n_items, m, lanes, rows), "fr_set_launch")

@@ -23,6 +23,8 @@ struct fr_ctx {
     hipStream_t own = nullptr;                           // used when the caller passes NULL
     std::map<std::pair<int, int>, std::pair<int, int>> launch;  // (I, m) -> (lanes, rows)
     bool timing = false;                                  // per-kernel event timing
+    int form = FR_FORM_LOG;                               // Sinkhorn form of the fixed-T forward
+    int absorb = 0;                                       // scaling form: forced absorption period
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
 };
@@ -90,6 +92,8 @@ int block_for(int L) { return L <= 64 ? 256 : L; }
 // Launch shape of the fused kernels for one problem.
 struct Shape {
     const FusedEntry* fe;
+    FwdLaunch fwd;       // fixed-T forward of the context's Sinkhorn form
+    int absorb;
     int L, R, mp, block, teams, grid;
     size_t lds_fwd, lds_bwd;
 };
@@ -171,6 +175,8 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     if (teams * per_team_bwd() > kMaxLds) return FR_E_UNSUPPORTED;
     block = teams * L;
     sh->fe = fe;
+    sh->fwd = (ctx->form == FR_FORM_SCALING && fe->fwds) ? fe->fwds : fe->fwd;
+    sh->absorb = ctx->absorb;
     sh->L = L;
     sh->R = R;
     sh->mp = mp;
@@ -309,6 +315,7 @@ FwdArgs fwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     a.L = sh.L;
     a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
     a.eps_ln2 = (float)((double)p->eps * M_LN2);
+    a.absorb = sh.absorb;
     return a;
 }
 
@@ -330,7 +337,7 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
 }
 
 fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
-    sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+    sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
     FR_TRY(hipGetLastError());
     return FR_OK;
 }
@@ -866,7 +873,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         b.cg_tol = kCgTol;
     }
     auto outer_step = [&]() {
-        (conv ? sh.fe->fwdc : sh.fe->fwd)(a, sh.grid, sh.block, sh.lds_fwd, s);
+        (conv ? sh.fe->fwdc : sh.fwd)(a, sh.grid, sh.block, sh.lds_fwd, s);
         launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
                       start_step, hdr, tol ? ADV_REP : ADV_REP_STEP, s);
         if (conv)
@@ -886,7 +893,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         for (auto& x : ev) FR_TRY(hipEventCreate(&x));
         for (int n = 0; n < N; ++n) {
             FR_TRY(hipEventRecord(ev[4 * n + 0], s));
-            sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+            sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
             FR_TRY(hipEventRecord(ev[4 * n + 1], s));
             launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
                           start_step, hdr, ADV_REP_STEP, s);
@@ -997,6 +1004,14 @@ fr_status fr_grad_converged(fr_ctx* ctx, const fr_problem* prob, const float* C,
     b.cg_tol = kCgTol;
     sh.fe->ibwd(b, sh.grid, sh.block, sh.lds_fwd, s);
     FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_ctx_set_form(fr_ctx* ctx, int32_t form, int32_t absorb_every) {
+    if (!ctx) return FR_E_NULL;
+    if ((form != FR_FORM_LOG && form != FR_FORM_SCALING) || absorb_every < 0) return FR_E_PARAM;
+    ctx->form = form;
+    ctx->absorb = absorb_every;
     return FR_OK;
 }
 
@@ -1304,7 +1319,7 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             float tot = 1e30f;
             for (int rep = 0; rep < 4; ++rep) {
                 FR_TRY(hipEventRecord(e0, s));
-                sh.fe->fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
+                sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
                 launch_impact(a.y, p.n_users, I, (double*)(w + Lw.partial), Lw.nchunk, impw,
                               nullptr, nullptr, 0, (WsHeader*)(w + Lw.hdr), 0, s);
                 sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);

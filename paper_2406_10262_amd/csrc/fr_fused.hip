@@ -627,6 +627,227 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, int64_t u_first, floa
 }
 
 // ---------------------------------------------------------------------------
+// Scaling form of the forward: the matrix-scaling iteration of Sinkhorn (the
+// form of the algorithm Section 3 cites), stabilised by absorbing the
+// scalings into log-domain potentials.  The registers hold the kernel
+//   Kt_ik = 2^(a_ik + gam_k + ph_i)
+// for absorbed potentials (gam, ph), and an iteration updates scalings only:
+//   u_i = 1 / sum_k Kt_ik v_k,      v_k = b_k / sum_i Kt_ik u_i,
+// the same iterates as the log-domain form (P^t = Kt diag(v^{t-1}) scaled by
+// u^t, gamma^t = gam + log2 v^t) at two multiply-adds per cell and no
+// exponential.  When a column scaling leaves [2^-32, 2^32] (or every
+// `absorb` iterations, if set), the scalings move into the potentials and Kt
+// is rebuilt from the costs in HBM: the log-domain step, one exponential per
+// cell.  Padded columns have b = 0, so their scaling stays 0 and they add
+// nothing to the row sums.
+constexpr float kScaleHi = 4294967296.0f;           // 2^32
+constexpr float kScaleLo = 1.0f / 4294967296.0f;    // 2^-32
+
+// Kt of the lane's rows from the costs in HBM: a = c c2 - off (the centring
+// offsets of load_costs), Kt = 2^(a + gam + ph).
+template <int MP, int R>
+__device__ __forceinline__ void build_kernel(const float* C, int64_t u, const Team& tm, int I,
+                                             int m, float c2, const float (&om)[R],
+                                             const float (&off)[R], const float (&gam)[MP],
+                                             const float (&ph)[R], float (&kt)[R][MP]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        const bool valid = om[j] > 0.f;
+        const float* src = C + (u * I + (valid ? i : 0)) * (int64_t)m;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            const float c = valid ? src[k < m ? k : m - 1] : 0.f;
+            kt[j][k] = ex2((fmaf(c, c2, -off[j]) + gam[k]) + ph[j]);
+        }
+    }
+}
+
+// Row half-step of the scaling form: u_j = 1 / sum_k Kt_jk v_k.
+template <int MP, int R>
+__device__ __forceinline__ void scale_rows(const float (&kt)[R][MP], const float (&v)[MP],
+                                           float (&u)[R]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float ps[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MP; ++k) ps[k & 3] = fmaf(kt[j][k], v[k], ps[k & 3]);
+        u[j] = rcp((ps[0] + ps[1]) + (ps[2] + ps[3]));
+    }
+}
+
+template <int MP, int R, bool WIDE>
+__device__ __forceinline__ void fwds_body(const FwdArgs& a, int64_t u_first, float* smem) {
+    const Team tm = make_team(a.L);
+    const int64_t u = u_first + tm.team;
+    const bool active = tm.team < (int)(blockDim.x / a.L) && u < a.U;
+    const int I = a.I, m = a.m;
+    float* red = smem + tm.team * (2 * tm.W * MP);
+    const float bd = (float)(I - m + 1);
+
+    float kt[R][MP], om[R], off[R];
+    load_costs<MP, R>(a.C, u, active, tm, I, m, a.c2, kt, om, off);
+
+    float gam[MP], v[MP], ph[R], us[R];
+    Cols<MP, WIDE> cs;
+    cs.init(tm, m, lg2(bd), 1.0f / bd, gam);
+    [[maybe_unused]] float bk[MP];
+    [[maybe_unused]] float vd = 0.f, bc = 0.f;
+    if constexpr (WIDE) {
+        bc = cs.live ? rcp(cs.ibc) : 0.f;
+        vd = cs.live ? 1.f : 0.f;
+        spread_owned<MP>(vd, v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            bk[k] = (k < m) ? ((k == m - 1) ? bd : 1.f) : 0.f;
+            v[k] = fminf(bk[k], 1.f);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        ph[j] = 0.f;
+        us[j] = 1.f;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) kt[j][k] = ex2(kt[j][k] + gam[k]);
+    }
+
+    float* hist = (a.hist != nullptr && active) ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
+    // base-2 column potentials gamma = gam + log2 v (kNeg on padding)
+    auto put_hist = [&](float* dst) {
+        if constexpr (WIDE) {
+            if (tm.wt == 0 && cs.col >= 0) dst[cs.col] = fmaxf(cs.gd + lg2(vd), kNeg);
+        } else {
+            if (tm.lt == 0) {
+#pragma unroll
+                for (int k = 0; k < MP; ++k) dst[k] = fmaxf(gam[k] + lg2(v[k]), kNeg);
+            }
+        }
+    };
+    if (hist) put_hist(hist);
+
+    for (int t = 1; t <= a.T; ++t) {
+        scale_rows<MP, R>(kt, v, us);
+        float w[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) w[j] = us[j] * om[j];
+        bool bad;
+        if constexpr (WIDE) {
+            float q[n_slots(MP)];
+            __builtin_amdgcn_sched_barrier(0);
+            for_chunks<MP>([&](auto ch) {
+                constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+                float p[ci.n];
+#pragma unroll
+                for (int kk = 0; kk < ci.n; ++kk) p[kk] = 0.f;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+#pragma unroll
+                    for (int kk = 0; kk < ci.n; ++kk) p[kk] = fmaf(kt[j][ci.k0 + kk], w[j], p[kk]);
+                }
+                scatter_chunk<MP, decltype(ch)::value>(p, q);
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            const float tot = wide_total<MP>(q, tm, cs.col, red, t & 1);
+            vd = bc * rcp(fmaxf(tot, kTiny));
+            bad = wave_any(cs.live && !(vd >= kScaleLo && vd <= kScaleHi));
+            spread_owned<MP>(vd, v);
+        } else {
+            float acc[MP];
+#pragma unroll
+            for (int k = 0; k < MP; ++k) acc[k] = 0.f;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+#pragma unroll
+                for (int k = 0; k < MP; ++k) acc[k] = fmaf(kt[j][k], w[j], acc[k]);
+            }
+            group_allreduce<MP>(acc, tm.L);
+            float hi = 0.f, lo = 1.f;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                v[k] = bk[k] * rcp(fmaxf(acc[k], kTiny));
+                hi = fmaxf(hi, v[k]);
+                lo = fminf(lo, v[k] > 0.f ? v[k] : 1.f);
+            }
+            bad = wave_any(!(hi <= kScaleHi) || lo < kScaleLo);
+        }
+        if (bad || (a.absorb > 0 && t % a.absorb == 0)) {
+            // move the scalings into the potentials and rebuild Kt (log-domain step)
+            if constexpr (WIDE) {
+                if (cs.live) cs.gd += lg2(vd);
+                vd = cs.live ? 1.f : 0.f;
+                spread_owned<MP>(cs.gd, gam);
+                spread_owned<MP>(vd, v);
+            } else {
+#pragma unroll
+                for (int k = 0; k < MP; ++k) {
+                    gam[k] = (v[k] > 0.f) ? gam[k] + lg2(v[k]) : gam[k];
+                    v[k] = fminf(bk[k], 1.f);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                ph[j] += lg2(us[j]);
+                us[j] = 1.f;
+            }
+            build_kernel<MP, R>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, gam, ph, kt);
+        }
+        if (hist) {
+            if (t % a.K == 0)
+                put_hist(hist + (int64_t)(t / a.K) * a.hs);
+            else if (t == a.T)
+                put_hist(hist + (int64_t)(a.nck - 1) * a.hs);
+        }
+    }
+
+    const int mo = opaque_u(m);
+    float ek[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) ek[k] = (k < mo - 1) ? a.e[k] : 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        if (!(active && i < I)) continue;
+        const int64_t row = u * I + i;
+        float yy = 0.f;
+        if (a.X && a.x_bf16) {
+            uint16_t* dst = (uint16_t*)a.X + row * m;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                const float x = (kt[j][k] * v[k]) * us[j];
+                yy = fmaf(ek[k], x, yy);
+                if (k < mo) dst[k] = to_bf16(x);
+            }
+        } else if (a.X) {
+            float* dst = (float*)a.X + row * m;
+#pragma unroll
+            for (int k = 0; k < MP; ++k) {
+                const float x = (kt[j][k] * v[k]) * us[j];
+                yy = fmaf(ek[k], x, yy);
+                if (k < mo) dst[k] = x;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) yy = fmaf(ek[k], kt[j][k] * v[k], yy);
+            yy *= us[j];
+        }
+        if (a.y) a.y[row] = a.r[row] * yy;
+        const float phi = ph[j] + lg2(us[j]) - off[j];
+        if (a.pot) a.pot[u * (int64_t)(I + m) + i] = phi * a.eps_ln2;
+        if (a.phi) a.phi[row] = phi;
+    }
+    if (a.pot && active) {
+        if constexpr (WIDE) {
+            if (tm.wt == 0 && cs.live) a.pot[u * (int64_t)(I + m) + I + cs.col] = (cs.gd + lg2(vd)) * a.eps_ln2;
+        } else if (tm.lt == 0) {
+#pragma unroll
+            for (int k = 0; k < MP; ++k)
+                if (k < mo) a.pot[u * (int64_t)(I + m) + I + k] = (gam[k] + lg2(v[k])) * a.eps_ln2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward pieces.  Reverse of iteration t for the lane's rows: gp = gamma^{t-1},
 // gh_k = gbar_k / sig^t_k; cb += P (gh + fbar); the lane's share of
 // sum_i P_ik fbar_i goes to acc (or, recompute variant, to the scattered q).
@@ -1203,6 +1424,14 @@ __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
                                                      smem);
 }
 
+// Scaling-form forward (same iterates as k_fwd).
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_fwds(FwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    fwds_body<MP, R, WIDE>(a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
+}
+
 // Converged-map forward: warm start from a.gw, stop at tolerance a.tol.
 template <int MP, int R, int LB, bool WIDE>
 __global__ __launch_bounds__(LB) void k_fwdc(FwdArgs a) {
@@ -1303,6 +1532,10 @@ void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s
     hipLaunchKernelGGL((k_bwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
 template <int MP, int R, int LB, bool WIDE>
+void launch_fwds(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwds<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
+}
+template <int MP, int R, int LB, bool WIDE>
 void launch_fwdc(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_fwdc<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
@@ -1324,6 +1557,7 @@ constexpr FusedEntry entry() {
                           &launch_bwd<FR_MP, R, LB, WIDE>,
                           &launch_fwdc<FR_MP, R, LB, WIDE>,
                           &launch_ibwd<FR_MP, R, LB, WIDE>,
+                          &launch_fwds<FR_MP, R, LB, WIDE>,
                           &launch_bfwd<FR_MP, R, WIDE>,
                           &launch_bbwd<FR_MP, R, WIDE>,
                           &occupancy_bfwd<FR_MP, R, WIDE>,
@@ -1332,7 +1566,7 @@ constexpr FusedEntry entry() {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,
                           &launch_fwdc<FR_MP, R, LB, WIDE>, &launch_ibwd<FR_MP, R, LB, WIDE>,
-                          nullptr, nullptr, nullptr, nullptr};
+                          &launch_fwds<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr};
     }
 }
 

@@ -37,6 +37,7 @@ struct FwdArgs {
     float* phi;            // [U][I] base-2 row potentials of the uncentred costs (or null)
     int64_t* iters;        // sum of the iterations used, added per consumer (or null)
     float tol;             // > 0: stop a consumer once no potential moves by more than tol
+    int absorb;            // scaling form: also absorb every `absorb` iterations (0: on range only)
     int64_t U;
     int I, m, T, K, nck, hs, L, x_bf16;
     float c2;              // -1 / (eps ln 2): exponent scale of a cost
@@ -91,6 +92,7 @@ struct FusedEntry {
     BwdLaunch bwd;
     FwdLaunch fwdc;     // converged-map forward (warm start, tolerance)
     BwdLaunch ibwd;     // implicit-function gradient at a converged plan
+    FwdLaunch fwds;     // scaling-form forward (same iterates as fwd)
     BFwdLaunch bfwd;    // persistent batched forms (launch bound 256 only)
     BBwdLaunch bbwd;
     Occupancy occ_bfwd;
