@@ -12,6 +12,8 @@ with the GPU path (``paper_2406_10262_amd``) and never imports it.
 * ``oracle.metrics`` -- the evaluation metrics of a plan.
 * ``oracle.warm`` -- Algorithm 1 on the converged map: warm-started Sinkhorn
   and the implicit-function gradient.
+* ``oracle.baselines`` -- the MaxRele and NSW(Greedy) rankings of the
+  comparison in Section 4.1.
 """
 from .core import (  # noqa: F401
     build_oracle, forward, forward_converge, forward_warm, impact, nsw, grad, adam, gd, solve,

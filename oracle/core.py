@@ -66,6 +66,8 @@ def _load():
             lib.fro_solve.argtypes = [i64, i32, i32, P, P, dbl, i32, i32, i32, dbl, dbl, dbl,
                                       dbl, P, P, P, i64, P, P, P, dbl, P, P]
             lib.fro_num_threads.restype = i32
+            lib.fro_maxrele.argtypes = [i64, i32, i32, P, P]
+            lib.fro_greedy.argtypes = [i64, i32, i32, P, P, P, P]
             _lib = lib
     return _lib
 

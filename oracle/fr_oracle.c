@@ -440,3 +440,79 @@ ORC_EXPORT int fro_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------------
+ * Baselines of the comparison in Section 4.1 (MaxRele, NSW(Greedy)).
+ *
+ * Both produce deterministic rankings: sel[u][k] is the item consumer u sees
+ * at real position k (k < m-1, row-major [U][m-1]); every item not selected
+ * by u goes to the dummy position.
+ *
+ * MaxRele: each consumer's items in descending order of relevance r(u,i);
+ * equal relevances in increasing item index.
+ *
+ * NSW(Greedy): the paper says only that greedy picks items by F(X) for each
+ * position.  Reading taken: the real positions are filled in order
+ * k = 0 .. m-2; at each position the consumers choose in index order; a
+ * consumer takes, among the items it has not placed yet, the one whose
+ * placement at k raises F = sum_i log Imp_i (Eq. objF) the most.  Placing i
+ * adds r(u,i) e(k) to Imp_i only, so the gain is
+ *     log(Imp_i + r e_k) - log(Imp_i) = log(1 + e_k r / Imp_i),
+ * increasing in r / Imp_i (e_k > 0 is the same for every candidate): the
+ * choice is the largest ratio r(u,i) / Imp_i, an item with Imp_i = 0 counting
+ * as +inf (its log goes from -inf to finite).  Equal ratios: larger r(u,i),
+ * then smaller index.  Imp is accumulated in FP64 in decision order and
+ * returned in imp[I].
+ * ------------------------------------------------------------------------- */
+ORC_EXPORT int fro_maxrele(int64_t U, int I, int m, const double* r, int32_t* sel) {
+    if (U < 1 || I < 2 || m < 2 || m > I || !r || !sel) return -1;
+    int* order = (int*)malloc(sizeof(int) * (size_t)I);
+    if (!order) return -2;
+    for (int64_t u = 0; u < U; ++u) {
+        const double* ru = r + u * I;
+        /* selection of the m-1 best, one position at a time */
+        for (int i = 0; i < I; ++i) order[i] = 0;   /* 1 = already placed */
+        for (int k = 0; k < m - 1; ++k) {
+            int best = -1;
+            for (int i = 0; i < I; ++i) {
+                if (order[i]) continue;
+                if (best < 0 || ru[i] > ru[best]) best = i;   /* ties keep the smaller index */
+            }
+            order[best] = 1;
+            sel[u * (m - 1) + k] = best;
+        }
+    }
+    free(order);
+    return 0;
+}
+
+ORC_EXPORT int fro_greedy(int64_t U, int I, int m, const double* r, const double* e,
+                          int32_t* sel, double* imp) {
+    if (U < 1 || I < 2 || m < 2 || m > I || !r || !e || !sel || !imp) return -1;
+    for (int i = 0; i < I; ++i) imp[i] = 0.0;
+    for (int k = 0; k < m - 1; ++k) {
+        for (int64_t u = 0; u < U; ++u) {
+            const double* ru = r + u * I;
+            const int32_t* mine = sel + u * (m - 1);
+            int best = -1;
+            double best_key = 0.0;
+            for (int i = 0; i < I; ++i) {
+                int placed = 0;
+                for (int j = 0; j < k; ++j) placed |= (mine[j] == i);
+                if (placed) continue;
+                const double key = (imp[i] > 0.0) ? ru[i] / imp[i] : INFINITY;
+                int better;
+                if (best < 0) better = 1;
+                else if (key != best_key) better = key > best_key;
+                else better = ru[i] > ru[best];   /* then the smaller index stays */
+                if (better) {
+                    best = i;
+                    best_key = key;
+                }
+            }
+            sel[u * (m - 1) + k] = best;
+            imp[best] += ru[best] * e[k];
+        }
+    }
+    return 0;
+}
