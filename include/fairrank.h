@@ -116,9 +116,9 @@ void fr_ctx_destroy(fr_ctx* ctx);
  * backward's recomputation keep the log domain).  Both forms compute the same
  * T iterates (Section 3's Sinkhorn iteration from g = 0); they differ in
  * arithmetic only.
- *   FR_FORM_LOG     (default) log-domain: one base-2 exponential per cell and
+ *   FR_FORM_LOG     log-domain: one base-2 exponential per cell and
  *                   iteration on centred scaled costs.
- *   FR_FORM_SCALING matrix scaling u = 1/(K v), v = b/(K^T u) on a kernel
+ *   FR_FORM_SCALING (default) matrix scaling u = 1/(K v), v = b/(K^T u) on a kernel
  *                   K = 2^(a + gamma + phi) held in registers: two multiply-adds
  *                   per cell and iteration, no exponential; the scalings are
  *                   absorbed into the potentials (and K rebuilt from C, one
@@ -156,6 +156,31 @@ fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
  * (double, either optional).  X need not be a Sinkhorn output. */
 fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,
                  double* imp, double* F, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- baselines */
+/* The deterministic rankings compared with Algorithm 1 in Section 4.1.  Both
+ * write sel [U][m-1] int32 (device): the item each consumer sees at each real
+ * position; every other item goes to the dummy position.  X (optional, NULL =
+ * not written) receives the 0/1 plan [U][I][m] in x_dtype, a feasible point of
+ * problem otp's polytope.  Asynchronous on the stream; argument errors return
+ * before anything is enqueued (the problem is checked as for fr_step; eps and
+ * T are not used).
+ *
+ * fr_rank_maxrele: MaxRele -- each consumer's items in descending order of
+ *   relevance (equal relevances by item index).  One wave per consumer.
+ * fr_rank_greedy: NSW(Greedy).  The paper says only that greedy picks items
+ *   by F(X) for each position; the rule fixed here: positions k = 0..m-2 in
+ *   order, consumers in index order within a position, each taking the item
+ *   it has not placed yet whose placement raises F = sum_i log Imp_i (Eq.
+ *   objF) the most, i.e. the largest r_ui / Imp_i in FP64 (Imp_i = 0 counts as
+ *   +inf), then the larger r_ui, then the smaller index.  The U (m-1)
+ *   decisions form one chain and run in a single block.  imp (optional, FP64
+ *   [I], device) receives the impacts of the result, accumulated in decision
+ *   order. */
+fr_status fr_rank_maxrele(fr_ctx* ctx, const fr_problem* prob, int32_t* sel, void* X,
+                          int32_t x_dtype, void* stream);
+fr_status fr_rank_greedy(fr_ctx* ctx, const fr_problem* prob, int32_t* sel, void* X,
+                         int32_t x_dtype, double* imp, void* stream);
 
 /* Evaluation metrics of a plan X [U][I][m] (x_dtype), from the list of
  * evaluation metrics in Section 4.1.  With W_uj = sum_{k<m-1} e_k x_ujk and

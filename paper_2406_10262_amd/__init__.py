@@ -22,7 +22,7 @@ import torch
 __all__ = [
     "load", "library_path", "FairRankError", "Context", "Problem", "step", "nsw",
     "backward", "solve", "solve_plain", "solve_batched", "SinkhornNSW", "sinkhorn_nsw", "metrics",
-    "grad_converged",
+    "grad_converged", "rank_maxrele", "rank_greedy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +96,8 @@ def load():
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_ctx_set_form.argtypes = [P, I32, I32]
+    lib.fr_rank_maxrele.argtypes = [P, PP, P, P, I32, P]
+    lib.fr_rank_greedy.argtypes = [P, PP, P, P, I32, P, P]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.fr_workspace_bytes_metrics.argtypes = [PP, ctypes.POINTER(SZ)]
     lib.fr_solve_progress.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
@@ -107,7 +109,8 @@ def load():
                  "fr_nsw", "fr_backward", "fr_solve", "fr_solve_plain", "fr_sync_status",
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
                  "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics",
-                 "fr_solve_progress", "fr_grad_converged", "fr_ctx_set_form"):
+                 "fr_solve_progress", "fr_grad_converged", "fr_ctx_set_form",
+                 "fr_rank_maxrele", "fr_rank_greedy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -158,9 +161,9 @@ class Context:
             self._ws = ws
         return self._ws
 
-    def set_form(self, form: str = "log", absorb_every: int = 0):
-        """fr_ctx_set_form: "log" (log-domain) or "scaling" (matrix scaling with
-        absorption) for the fixed-T forward of later calls."""
+    def set_form(self, form: str = "scaling", absorb_every: int = 0):
+        """fr_ctx_set_form: "scaling" (matrix scaling with absorption; the
+        default) or "log" (log-domain) for the fixed-T forward of later calls."""
         code = {"log": FR_FORM_LOG, "scaling": FR_FORM_SCALING}[form]
         _check(load().fr_ctx_set_form(self.handle, code, int(absorb_every)), "fr_ctx_set_form")
 
@@ -497,3 +500,34 @@ def _default_ctx(device) -> Context:
     if idx not in _ctxs:
         _ctxs[idx] = Context(idx)
     return _ctxs[idx]
+
+
+def _rank(fn, ctx: Context, prob: Problem, want_X: bool, x_dtype: str, want_imp: bool):
+    U, I, m = prob.U, prob.I, prob.m
+    dev = ctx.device
+    sel = torch.empty((U, m - 1), dtype=torch.int32, device=dev)
+    X = None
+    if want_X:
+        X = torch.empty((U, I, m), dtype=torch.bfloat16 if x_dtype == "bf16" else torch.float32,
+                        device=dev)
+    imp = torch.empty(I, dtype=torch.float64, device=dev) if want_imp else None
+    p = prob.c()
+    xd = FR_BF16 if x_dtype == "bf16" else FR_F32
+    if fn == "greedy":
+        code = load().fr_rank_greedy(ctx.handle, ctypes.byref(p), _ptr(sel), _ptr(X), xd,
+                                     _ptr(imp), _stream(dev))
+    else:
+        code = load().fr_rank_maxrele(ctx.handle, ctypes.byref(p), _ptr(sel), _ptr(X), xd,
+                                      _stream(dev))
+    _check(code, "fr_rank_" + fn)
+    return {"sel": sel, "X": X, "imp": imp}
+
+
+def rank_maxrele(ctx: Context, prob: Problem, want_X: bool = True, x_dtype: str = "f32"):
+    """fr_rank_maxrele: the MaxRele baseline.  Returns dict(sel [U][m-1], X)."""
+    return _rank("maxrele", ctx, prob, want_X, x_dtype, False)
+
+
+def rank_greedy(ctx: Context, prob: Problem, want_X: bool = True, x_dtype: str = "f32"):
+    """fr_rank_greedy: the NSW(Greedy) baseline.  Returns dict(sel, X, imp)."""
+    return _rank("greedy", ctx, prob, want_X, x_dtype, True)

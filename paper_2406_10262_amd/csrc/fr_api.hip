@@ -23,7 +23,7 @@ struct fr_ctx {
     hipStream_t own = nullptr;                           // used when the caller passes NULL
     std::map<std::pair<int, int>, std::pair<int, int>> launch;  // (I, m) -> (lanes, rows)
     bool timing = false;                                  // per-kernel event timing
-    int form = FR_FORM_LOG;                               // Sinkhorn form of the fixed-T forward
+    int form = FR_FORM_SCALING;                           // Sinkhorn form of the fixed-T forward
     int absorb = 0;                                       // scaling form: forced absorption period
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
@@ -1003,6 +1003,36 @@ fr_status fr_grad_converged(fr_ctx* ctx, const fr_problem* prob, const float* C,
     b.cg_max = cg_cap(prob->m, cg_iters);
     b.cg_tol = kCgTol;
     sh.fe->ibwd(b, sh.grid, sh.block, sh.lds_fwd, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_rank_maxrele(fr_ctx* ctx, const fr_problem* prob, int32_t* sel, void* X,
+                          int32_t x_dtype, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!sel) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    launch_maxrele(prob->r, prob->n_users, prob->n_items, prob->m, sel, s);
+    if (X) launch_plan_from_sel(sel, prob->n_users, prob->n_items, prob->m, X, x_dtype == FR_BF16, s);
+    FR_TRY(hipGetLastError());
+    return FR_OK;
+}
+
+fr_status fr_rank_greedy(fr_ctx* ctx, const fr_problem* prob, int32_t* sel, void* X,
+                         int32_t x_dtype, double* imp, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!sel) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    FR_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = pick_stream(ctx, stream);
+    launch_greedy(prob->r, prob->e, prob->n_users, prob->n_items, prob->m, sel, imp, s);
+    if (X) launch_plan_from_sel(sel, prob->n_users, prob->n_items, prob->m, X, x_dtype == FR_BF16, s);
     FR_TRY(hipGetLastError());
     return FR_OK;
 }

@@ -827,9 +827,9 @@ __device__ __forceinline__ void fwds_body(const FwdArgs& a, int64_t u_first, flo
                 if (k < mo) dst[k] = x;
             }
         } else {
+            // the same products as with X, so the impacts do not depend on it
 #pragma unroll
-            for (int k = 0; k < MP; ++k) yy = fmaf(ek[k], kt[j][k] * v[k], yy);
-            yy *= us[j];
+            for (int k = 0; k < MP; ++k) yy = fmaf(ek[k], (kt[j][k] * v[k]) * us[j], yy);
         }
         if (a.y) a.y[row] = a.r[row] * yy;
         const float phi = ph[j] + lg2(us[j]) - off[j];

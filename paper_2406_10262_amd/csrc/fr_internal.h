@@ -171,4 +171,11 @@ void plain_backward_update(float* C, const float* r, const float* e, int64_t U, 
                            float eps, int T, const PlainBufs& b, float* mom, float* vel, int rule,
                            float lr, float b1, float b2, float aeps, bool apply, hipStream_t s);
 
+// Baseline rankings (fr_baselines.hip).
+void launch_maxrele(const float* r, int64_t U, int I, int m, int32_t* sel, hipStream_t s);
+void launch_greedy(const float* r, const float* e, int64_t U, int I, int m, int32_t* sel,
+                   double* imp, hipStream_t s);
+void launch_plan_from_sel(const int32_t* sel, int64_t U, int I, int m, void* X, int bf16,
+                          hipStream_t s);
+
 }  // namespace fr

@@ -11,9 +11,12 @@ from gpu_util import F_REL, GRAD_REL, device_problem, rel
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx(fr):
-    return fr.Context(0)
+@pytest.fixture(scope="module", params=["scaling", "log"])
+def ctx(fr, request):
+    """Every solve runs with each Sinkhorn form of the forward."""
+    c = fr.Context(0)
+    c.set_form(request.param)
+    return c
 
 
 def _grad_case(fr, ctx, inst, C, K, launch=None):

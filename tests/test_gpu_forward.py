@@ -11,9 +11,12 @@ from gpu_util import assert_step_close, device_problem, oracle_step
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx(fr):
-    return fr.Context(0)
+@pytest.fixture(scope="module", params=["scaling", "log"])
+def ctx(fr, request):
+    """Both Sinkhorn forms compute the same iterates; every test runs on each."""
+    c = fr.Context(0)
+    c.set_form(request.param)
+    return c
 
 
 def _run(fr, ctx, r, e, eps, T, C, launch=None, want_X=True, x_dtype="f32"):

@@ -1,5 +1,5 @@
-"""The scaling form of the Sinkhorn forward (fr_ctx_set_form FR_FORM_SCALING)
-against the FP64 oracle.  It computes the same T iterates as the log-domain
+"""The scaling form of the Sinkhorn forward (fr_ctx_set_form FR_FORM_SCALING,
+the default) against the FP64 oracle, with its absorption forced.  It computes the same T iterates as the log-domain
 form (Section 3's Sinkhorn iteration from g = 0), so the oracle and the bars
 are those of the log-domain forward: plans 1e-5, F 1e-6, impacts 2e-6.
 
@@ -25,9 +25,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def ctx(fr):
-    c = fr.Context(0)
-    yield c
-    c.set_form("log")
+    return fr.Context(0)
 
 
 def _step(fr, ctx, inst, C, absorb, launch=None, x_dtype="f32", T=None):
@@ -120,13 +118,13 @@ def test_scaling_bf16_and_subsample(fr, ctx):
 
 def test_scaling_solve_C2_trajectory(fr, ctx):
     """The full 2000 x 100 x 10 solve (T 200, 100 Adam steps) with the scaling
-    forward and the log-domain reverse sweep, against the stored FP64 oracle
-    trajectory."""
+    forward absorbing every fourth iteration and the log-domain reverse sweep,
+    against the stored FP64 oracle trajectory."""
     with open(os.path.join(os.path.dirname(__file__), "golden", "c2_trajectory.json")) as fh:
         gold = json.load(fh)
     inst = W.config("C2")
-    print("case scaling C2 solve", flush=True)
-    ctx.set_form("scaling", 0)
+    print("case scaling C2 solve, absorbing every 4th iteration", flush=True)
+    ctx.set_form("scaling", 4)
     prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
     res = fr.solve(ctx, prob, inst.N, float(inst.lr))
     Fh = res["F_hist"].cpu().numpy()
