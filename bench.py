@@ -43,7 +43,7 @@ import numpy as np  # noqa: E402
 # two accumulation FMAs).
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 PEAK_SLOTS = CUS * SIMDS * LANES * CLOCK          # 3.93e13 lane-slots/s
-FWD_SLOTS = 5
+FWD_SLOTS = {"log": 5, "scaling": 2}   # scaling form: the two multiply-adds of u and v
 BWD_SLOTS = 8
 HBM_PEAK = 8.0e12
 
@@ -75,11 +75,12 @@ def _lib_timing(lib):
     lib.fr_ctx_kernel_times.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
 
 
-def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name):
+def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
     """Per-kernel mean launch times with HIP events (one solve in timing
     mode), and the roofline of the dominant kernel."""
     import torch
     _lib_timing(lib)
+    ctx.set_form(form)
     lib.fr_ctx_set_timing(ctx.handle, 1)
     fr.solve(ctx, prob, N, lr, want_X=False)
     torch.cuda.synchronize()
@@ -89,10 +90,14 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name):
     lib.fr_ctx_set_timing(ctx.handle, 0)
     cells = prob.U * prob.I * prob.m
     per_launch = cells * (prob.T + 1)   # cell-iterations of one launch (incl. plan / init pass)
-    ks = {"k_fwd": (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS),
+    fk = "k_fwds" if form == "scaling" else "k_fwd"
+    ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS[form]),
           "k_bwd": (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS)}
     kernels = {k: {"avg_ms": v[0], "launches": v[1],
-                   "cell_iters_per_s": per_launch / (v[0] * 1e-3)} for k, v in ks.items()}
+                   "cell_iters_per_s": per_launch / (v[0] * 1e-3),
+                   "alg_slots_per_cell_iter": v[2],
+                   "alu_frac": per_launch * v[2] / (v[0] * 1e-3) / PEAK_SLOTS}
+               for k, v in ks.items()}
     dom = max(ks, key=lambda k: ks[k][0])
     avg_ms, _, slots = ks[dom]
     achieved = per_launch * slots / (avg_ms * 1e-3)
@@ -103,9 +108,54 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name):
             "model": f"{slots} non-transcendental VALU lane-slots per cell-iteration (the "
                      "exponential overlaps on its own half-rate pipe), U*I*m*(T+1) "
                      "cell-iterations per launch; peak = 256 CUs x 64 lanes x 2.4 GHz"}
-    print(f"bench: kernels fwd {ks['k_fwd'][0]:.3f} ms bwd {ks['k_bwd'][0]:.3f} ms per launch",
-          flush=True)
+    print(f"bench: kernels ({form} forward) fwd {ks[fk][0]:.3f} ms bwd {ks['k_bwd'][0]:.3f} ms "
+          "per launch", flush=True)
     return kernels, roof
+
+
+def bench_converged(fr, ctx, prob, N, lr, F_fixed, tol=1e-4):
+    """The converged-map form of Algorithm 1 on the same workload: warm-started
+    Sinkhorn to a potential tolerance (T as cap), implicit-function gradients."""
+    import torch
+    fr.solve(ctx, prob, N, lr, want_X=False, sinkhorn_tol=tol)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fr.solve(ctx, prob, N, lr, want_X=False, sinkhorn_tol=tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Fh = res["F_hist"].cpu().numpy()
+    its = res["sinkhorn_iters"]
+    print(f"bench: converged-map form {dt * 1e3:.1f} ms/solve, {its} Sinkhorn iterations",
+          flush=True)
+    return {"ms_per_solve": dt * 1e3, "sinkhorn_tol_log2": tol, "T_cap": prob.T,
+            "sinkhorn_iters": its,
+            "mean_iters_per_consumer_forward": its / (prob.U * (N + 1)),
+            "F_N": float(Fh[-1]), "F_N_fixed_T_form": float(F_fixed),
+            "form": "warm-started Sinkhorn to tolerance, implicit-function gradient (CG on the "
+                    "m x m Schur system per consumer), Adam"}
+
+
+def bench_baselines(fr, ctx, prob):
+    """MaxRele and NSW(Greedy) rankings of the same instance: GPU time, the
+    evaluation metrics of their plans and F (None if an item has no impact)."""
+    import torch
+    out = {}
+    for name, run in (("maxrele", fr.rank_maxrele), ("greedy", fr.rank_greedy)):
+        res = run(ctx, prob)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run(ctx, prob)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        met = fr.metrics(ctx, prob, res["X"], per_item=True)
+        v = met[0].cpu().numpy()
+        imp = met[2].cpu().numpy()
+        F = float(np.sum(np.log(imp))) if np.all(imp > 0) else None
+        out[name] = {"ms": dt * 1e3, "F": F, "user_utility": float(v[0]),
+                     "mean_max_envy": float(v[1]), "items_better": float(v[2]),
+                     "items_worse": float(v[3])}
+        print(f"bench: {name} {dt * 1e3:.2f} ms, F {F}", flush=True)
+    return out
 
 
 def measured_peaks(lib):
@@ -175,16 +225,26 @@ def bench_solve(args, fr, lib, dev, name):
     if name == "C5":
         nsw.update(c5_subsample_error(fr, dev, inst))
     kernels, roof = kernel_roofline(fr, lib, ctx, prob, min(N, 20), lr, inst.name)
+    kernels_log, _ = kernel_roofline(fr, lib, ctx, prob, min(N, 20), lr, inst.name, form="log")
+    ctx.set_form("scaling")
     desc = {"C1": "low-dimensional uniform-relevance", "C2": "low-rank-16 sigmoid relevance",
             "C5": "low-rank-32 sigmoid relevance, plans stored in BF16"}[name]
     config = {"workload": f"{inst.name}: U={U} consumers, I={I} items, m={m} positions "
                           f"(incl. dummy), {desc}, e_k=1/log2(k+1), eps={float(inst.eps):.4g}, "
                           f"T={T} Sinkhorn iterations, N={N} Adam steps (lr=0.1 eps), FP32 "
-                          f"log-domain Sinkhorn, FP64 impacts and log-NSW",
+                          f"Sinkhorn (scaling form with log-domain absorption; log-domain "
+                          f"reverse sweep), FP64 impacts and log-NSW",
               "step": "one full solve (N outer steps + final forward)",
               "cells": cells, "cell_iters_per_step": work}
     out = base_record(args, value, ms_per_step, config)
-    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics})
+    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics,
+                "log_domain_forward": {
+                    "k_fwd": kernels_log["k_fwd"],
+                    "note": "the same iterates with one exponential per cell-iteration; the "
+                            "solve above runs the scaling form (k_fwds)"}})
+    if name != "C5" and not args.skip_extras:
+        out["converged_map"] = bench_converged(fr, ctx, prob, N, lr, Fh[-1])
+        out["baselines"] = bench_baselines(fr, ctx, prob)
     if not args.skip_diag:
         out["measured_peaks"] = measured_peaks(lib)
     if not args.skip_plain and name != "C5":
@@ -443,6 +503,8 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-diag", action="store_true")
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="skip the converged-map and baseline legs")
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: only warm-up and timed fused solves")
     ap.add_argument("--copy-calibration", action="store_true",

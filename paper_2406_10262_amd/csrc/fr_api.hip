@@ -1253,16 +1253,19 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     const int2* dt1 = (const int2*)(w + P.d_tab1);
     const int2* dt2 = (const int2*)(w + P.d_tab2);
     std::vector<int> grid_f(ncls), grid_b(ncls);
+    const bool scaling = ctx->form == FR_FORM_SCALING;   // the batched forward follows the context
     for (int c = 0; c < ncls; ++c) {
         const int nit = (int)P.items[c].size();
-        grid_f[c] = std::max(1, std::min(nit, P.classes[c]->occ_bfwd(256, P.lds_fwd[c]) * cus));
+        const Occupancy occ_f = scaling ? P.classes[c]->occ_bfwds : P.classes[c]->occ_bfwd;
+        grid_f[c] = std::max(1, std::min(nit, occ_f(256, P.lds_fwd[c]) * cus));
         grid_b[c] = std::max(1, std::min(nit, P.classes[c]->occ_bbwd(256, P.lds_bwd[c]) * cus));
     }
     auto forward_phase = [&](const FwdArgs* descs) {
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 0);
         for (int c = 0; c < ncls; ++c)
-            P.classes[c]->bfwd(descs, ditems + item_off[c], (int)P.items[c].size(), counters + c,
-                               grid_f[c], 256, P.lds_fwd[c], s);
+            (scaling ? P.classes[c]->bfwds : P.classes[c]->bfwd)(
+                descs, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_f[c], 256,
+                P.lds_fwd[c], s);
         launch_impact_batched(drd, n_inst, dt1, (int)P.tab1.size(), dt2, (int)P.tab2.size(),
                               start_step, hdr, s);
     };

@@ -1460,7 +1460,7 @@ __global__ __launch_bounds__(LB) void k_ibwd(BwdArgs a) {
 // Persistent batched kernels: every block repeatedly takes the next work item
 // (instance, first consumer) from a global counter and runs the same team
 // body on it, until the list is exhausted.  Items are ordered longest first.
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 __global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
                                               const BatchItem* __restrict__ items, int n_items,
                                               unsigned* counter) {
@@ -1474,7 +1474,10 @@ __global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
         if (it >= n_items) break;
         const BatchItem bi = items[it];
         const FwdArgs a = descs[bi.inst];
-        fwd_body<MP, R, WIDE, recomp_fwd<R, 256, WIDE>()>(a, bi.u0, smem);
+        if constexpr (SCALE)
+            fwds_body<MP, R, WIDE>(a, bi.u0, smem);
+        else
+            fwd_body<MP, R, WIDE, recomp_fwd<R, 256, WIDE>()>(a, bi.u0, smem);
     }
 }
 
@@ -1496,20 +1499,21 @@ __global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
     }
 }
 
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 void launch_bfwd(const FwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bfwd<MP, R, WIDE>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+    hipLaunchKernelGGL((k_bfwd<MP, R, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
+                       ctr);
 }
 template <int MP, int R, bool WIDE>
 void launch_bbwd(const BwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_bbwd<MP, R, WIDE>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
 }
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 int occupancy_bfwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, WIDE>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, WIDE, SCALE>, block, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
@@ -1558,15 +1562,18 @@ constexpr FusedEntry entry() {
                           &launch_fwdc<FR_MP, R, LB, WIDE>,
                           &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_fwds<FR_MP, R, LB, WIDE>,
-                          &launch_bfwd<FR_MP, R, WIDE>,
+                          &launch_bfwd<FR_MP, R, WIDE, false>,
                           &launch_bbwd<FR_MP, R, WIDE>,
-                          &occupancy_bfwd<FR_MP, R, WIDE>,
-                          &occupancy_bbwd<FR_MP, R, WIDE>};
+                          &occupancy_bfwd<FR_MP, R, WIDE, false>,
+                          &occupancy_bbwd<FR_MP, R, WIDE>,
+                          &launch_bfwd<FR_MP, R, WIDE, true>,
+                          &occupancy_bfwd<FR_MP, R, WIDE, true>};
     } else {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,
                           &launch_fwdc<FR_MP, R, LB, WIDE>, &launch_ibwd<FR_MP, R, LB, WIDE>,
-                          &launch_fwds<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr};
+                          &launch_fwds<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, nullptr};
     }
 }
 

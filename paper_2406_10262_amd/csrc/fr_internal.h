@@ -97,6 +97,8 @@ struct FusedEntry {
     BBwdLaunch bbwd;
     Occupancy occ_bfwd;
     Occupancy occ_bbwd;
+    BFwdLaunch bfwds;   // batched scaling-form forward
+    Occupancy occ_bfwds;
 };
 
 // Instantiated column classes.  Each class is compiled in its own translation

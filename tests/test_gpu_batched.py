@@ -42,8 +42,6 @@ def adam_run(fr):
 
 def test_batched_equals_single_instance_solver(fr, adam_run):
     insts, probs, res, ctx = adam_run
-    # the batched kernels run the log-domain forward: so does the reference here
-    ctx.set_form("log")
     for j, (x, p) in enumerate(zip(insts, probs)):
         print(f"case instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
         one = fr.solve(ctx, p, 6, 0.003)
@@ -53,6 +51,21 @@ def test_batched_equals_single_instance_solver(fr, adam_run):
         Fb = res[j]["F_hist"].cpu().numpy()
         Fs = one["F_hist"].cpu().numpy()
         assert np.max(np.abs(Fb / Fs - 1)) <= 1e-14
+
+
+def test_batched_log_form_equals_single_instance_solver(fr):
+    """With the log-domain forward selected, the batched kernels run it too."""
+    insts = _instances()[:4] + _instances()[12:]
+    ctx = fr.Context(0)
+    ctx.set_form("log")
+    _pin_launch(ctx, insts)
+    probs = [device_problem(fr, x.r, x.e, x.eps, x.T) for x in insts]
+    print("case batched log-domain solve of", len(insts), "instances", flush=True)
+    res = fr.solve_batched(ctx, probs, 3, 0.003)
+    for j, p in enumerate(probs):
+        one = fr.solve(ctx, p, 3, 0.003)
+        assert torch.equal(res[j]["C"], one["C"])
+        assert torch.equal(res[j]["F_hist"], one["F_hist"])
 
 
 @pytest.mark.parametrize("j", [0, 3, 7, 12, 13])
@@ -84,9 +97,16 @@ def test_batched_gradient_ascent_matches_oracle(fr, j):
     print(f"case oracle GD instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
     ref = oracle.solve(x.r, x.e, float(x.eps), x.T, 4, rule="gd", lr=0.5)
     assert f_err(res[j]["F_hist"].cpu().numpy(), ref["F_hist"], x.I) <= F_REL
-    assert np.max(np.abs(res[j]["X"].double().cpu().numpy() - ref["X"])) <= 1e-5
+    # C_4 = C_0 + lr sum_n grad_n: per-step gradients within GRAD_REL = 1e-4 of
+    # their maximum bound C to ~1e-4 of max |C_4|
+    C = res[j]["C"].double().cpu().numpy()
     Cref = ref["C"]
-    assert np.max(np.abs(res[j]["C"].double().cpu().numpy() - Cref)) <= 1e-5 * np.max(np.abs(Cref))
+    assert np.max(np.abs(C - Cref)) <= 1e-4 * np.max(np.abs(Cref))
+    # the plan is exact to the forward bar at the GPU's own C_4, and follows the
+    # oracle's trajectory to the plan's sensitivity to that cost error
+    X = res[j]["X"].double().cpu().numpy()
+    assert np.max(np.abs(X - oracle.forward(C, float(x.eps), x.T))) <= 1e-5
+    assert np.max(np.abs(X - ref["X"])) <= 1e-4
 
 
 def test_batched_ignores_team_widths_that_do_not_tile_its_blocks(fr):

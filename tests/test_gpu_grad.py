@@ -65,16 +65,24 @@ def test_backward_checkpointed_against_oracle_and_fd(fr, setup, tag):
                   1e-4 * np.abs(fdr))
 
 
-def test_checkpoint_interval_does_not_change_the_gradient(fr, setup):
+@pytest.mark.parametrize("form,bar", [("log", 1e-5), ("scaling", GRAD_REL)])
+def test_checkpoint_interval_does_not_change_the_gradient(fr, setup, form, bar):
+    """K = 1 reads the forward's stored potentials, K > 1 rebuilds each
+    segment in the log domain from a checkpoint.  With the log-domain forward
+    both run the same arithmetic (bar: rounding of the reduction order); the
+    scaling forward's potentials carry their own FP32 rounding, so the bar is
+    the gradient tolerance."""
     d, inst, ctx, prob, points = setup
+    ctx.set_form(form)
     C = points["rand"]
     out = fr.step(ctx, prob, C)
     a, _ = fr.backward(ctx, prob, C, out["imp"], 1.0, want_dr=False, K=1)
     b, _ = fr.backward(ctx, prob, C, out["imp"], 1.0, want_dr=False, K=50)
     c, _ = fr.backward(ctx, prob, C, out["imp"], 1.0, want_dr=False, K=7)
+    ctx.set_form("scaling")
     scale = float(a.abs().max())
-    assert float((a - b).abs().max()) <= 1e-5 * scale
-    assert float((a - c).abs().max()) <= 1e-5 * scale
+    assert float((a - b).abs().max()) <= bar * scale
+    assert float((a - c).abs().max()) <= bar * scale
 
 
 def test_autograd_function(fr, setup):
