@@ -328,6 +328,7 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     a.I = p->n_items;
     a.m = p->m;
     a.T = p->sinkhorn_iters;
+    a.K = 1;   // every iterate kept; callers that checkpoint set K
     a.hs = registry().mp_for(p->m);
     a.L = sh.L;
     a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
