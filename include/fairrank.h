@@ -112,19 +112,24 @@ fr_status fr_ctx_create(int device, fr_ctx** out);
 void fr_ctx_destroy(fr_ctx* ctx);
 
 /* Form of the fixed-T Sinkhorn forward that every later call on this context
- * runs (fr_step, fr_solve, fr_autotune; the batched and plain solves and the
- * backward's recomputation keep the log domain).  Both forms compute the same
- * T iterates (Section 3's Sinkhorn iteration from g = 0); they differ in
- * arithmetic only.
+ * runs (fr_step, fr_solve, fr_solve_batched, fr_autotune; the plain solve and
+ * the backward's checkpoint recomputation keep the log domain).  Both forms
+ * compute the same T iterates (Section 3's Sinkhorn iteration from g = 0);
+ * they differ in arithmetic only.
  *   FR_FORM_LOG     log-domain: one base-2 exponential per cell and
  *                   iteration on centred scaled costs.
- *   FR_FORM_SCALING (default) matrix scaling u = 1/(K v), v = b/(K^T u) on a kernel
- *                   K = 2^(a + gamma + phi) held in registers: two multiply-adds
- *                   per cell and iteration, no exponential; the scalings are
- *                   absorbed into the potentials (and K rebuilt from C, one
- *                   exponential per cell) whenever a column scaling leaves
- *                   [2^-32, 2^32], and also every absorb_every iterations if
- *                   absorb_every > 0.
+ *   FR_FORM_SCALING (default) matrix scaling u = 1/(K v), v = b/(K^T u) on a
+ *                   kernel K = 2^(a + gamma + phi) held in registers: two
+ *                   multiply-adds per cell and iteration, no exponential; the
+ *                   scalings are absorbed into the potentials (and K rebuilt
+ *                   from C, one exponential per cell) whenever a column
+ *                   scaling leaves [2^-32, 2^32], and also every absorb_every
+ *                   iterations if absorb_every > 0.  With every iterate stored (K = 1)
+ *                   the reverse sweep (fr_backward, fr_solve) runs in the
+ *                   same form on launch shapes whose rows fit the registers
+ *                   (a reference kernel rebased from C when a column
+ *                   scaling leaves the range); other shapes keep the log
+ *                   domain.  The gradient is the same.
  * FR_E_PARAM for an unknown form or absorb_every < 0.  Host only. */
 fr_status fr_ctx_set_form(fr_ctx* ctx, int32_t form, int32_t absorb_every);
 

@@ -93,6 +93,7 @@ int block_for(int L) { return L <= 64 ? 256 : L; }
 struct Shape {
     const FusedEntry* fe;
     FwdLaunch fwd;       // fixed-T forward of the context's Sinkhorn form
+    BwdLaunch bwd;       // reverse sweep (the scaling form needs K = 1)
     int absorb;
     int L, R, mp, block, teams, grid;
     size_t lds_fwd, lds_bwd;
@@ -176,6 +177,10 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     block = teams * L;
     sh->fe = fe;
     sh->fwd = (ctx->form == FR_FORM_SCALING && fe->fwds) ? fe->fwds : fe->fwd;
+    // the scaling-form sweep where it keeps a row of products in registers; the
+    // two-pass (recompute) shapes spill more in that form and keep the log domain
+    sh->bwd = (ctx->form == FR_FORM_SCALING && K <= 1 && fe->bwds && !fe->recomp_b) ? fe->bwds
+                                                                                    : fe->bwd;
     sh->absorb = ctx->absorb;
     sh->L = L;
     sh->R = R;
@@ -329,6 +334,7 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     a.m = p->m;
     a.T = p->sinkhorn_iters;
     a.K = 1;   // every iterate kept; callers that checkpoint set K
+    a.absorb = sh.absorb;
     a.hs = registry().mp_for(p->m);
     a.L = sh.L;
     a.c2 = (float)(-1.0 / ((double)p->eps * M_LN2));
@@ -344,7 +350,7 @@ fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
 }
 
 fr_status launch_bwd(const Shape& sh, const BwdArgs& a, hipStream_t s) {
-    sh.fe->bwd(a, sh.grid, sh.block, sh.lds_bwd, s);
+    sh.bwd(a, sh.grid, sh.block, sh.lds_bwd, s);
     FR_TRY(hipGetLastError());
     return FR_OK;
 }
@@ -880,7 +886,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         if (conv)
             sh.fe->ibwd(b, sh.grid, sh.block, sh.lds_fwd, s);
         else
-            sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+            sh.bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
         if (tol)
             launch_gnorm_update(b.dC, C, adam_m, adam_v, ncell, optim->rule, optim->lr,
                                 optim->beta1, optim->beta2, optim->adam_eps,
@@ -899,7 +905,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
             launch_impact(y, prob->n_users, prob->n_items, partial, Lw.nchunk, imp, nullptr, F_hist,
                           start_step, hdr, ADV_REP_STEP, s);
             FR_TRY(hipEventRecord(ev[4 * n + 2], s));
-            sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+            sh.bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
             FR_TRY(hipEventRecord(ev[4 * n + 3], s));
         }
         FR_TRY(hipGetLastError());
@@ -1255,11 +1261,16 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     const int2* dt2 = (const int2*)(w + P.d_tab2);
     std::vector<int> grid_f(ncls), grid_b(ncls);
     const bool scaling = ctx->form == FR_FORM_SCALING;   // the batched forward follows the context
+    // and so does the reverse sweep, under the single-instance rule (K = 1, no recompute)
+    std::vector<char> sweep_s(ncls);
+    for (int c = 0; c < ncls; ++c)
+        sweep_s[c] = scaling && K <= 1 && P.classes[c]->bbwds && !P.classes[c]->recomp_b;
     for (int c = 0; c < ncls; ++c) {
         const int nit = (int)P.items[c].size();
         const Occupancy occ_f = scaling ? P.classes[c]->occ_bfwds : P.classes[c]->occ_bfwd;
         grid_f[c] = std::max(1, std::min(nit, occ_f(256, P.lds_fwd[c]) * cus));
-        grid_b[c] = std::max(1, std::min(nit, P.classes[c]->occ_bbwd(256, P.lds_bwd[c]) * cus));
+        const Occupancy occ_b = sweep_s[c] ? P.classes[c]->occ_bbwds : P.classes[c]->occ_bbwd;
+        grid_b[c] = std::max(1, std::min(nit, occ_b(256, P.lds_bwd[c]) * cus));
     }
     auto forward_phase = [&](const FwdArgs* descs) {
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 0);
@@ -1273,8 +1284,9 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     auto backward_phase = [&]() {
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 1);
         for (int c = 0; c < ncls; ++c)
-            P.classes[c]->bbwd(dba, ditems + item_off[c], (int)P.items[c].size(), counters + c,
-                               grid_b[c], 256, P.lds_bwd[c], s);
+            (sweep_s[c] ? P.classes[c]->bbwds : P.classes[c]->bbwd)(
+                dba, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_b[c], 256,
+                P.lds_bwd[c], s);
     };
 
     hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, hdr, start_step);
@@ -1356,7 +1368,7 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
                 sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
                 launch_impact(a.y, p.n_users, I, (double*)(w + Lw.partial), Lw.nchunk, impw,
                               nullptr, nullptr, 0, (WsHeader*)(w + Lw.hdr), 0, s);
-                sh.fe->bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
+                sh.bwd(b, sh.grid, sh.block, sh.lds_bwd, s);
                 FR_TRY(hipEventRecord(e1, s));
                 FR_TRY(hipEventSynchronize(e1));
                 FR_TRY(hipGetLastError());

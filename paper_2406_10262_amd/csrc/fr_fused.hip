@@ -974,6 +974,47 @@ __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][M
     }
 }
 
+// Backward epilogue for the lane's rows: writes gF * dF/dC, or applies Adam /
+// ascent to C in place (re-reading C from HBM: the registers hold transformed
+// costs).
+template <int MP, int R>
+__device__ __forceinline__ void bwd_epilogue(const BwdArgs& a, const float (&cb)[R][MP], int64_t u,
+                                             const Team& tm) {
+    const int I = a.I, m = a.m;
+    const int mo = opaque_u(m);
+    float bc1 = 1.f, bc2 = 1.f;
+    if (a.Cw && a.rule == 0) {
+        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
+        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
+        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        if (i >= I) continue;
+        const int64_t base = (u * I + i) * (int64_t)m;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            if (k >= mo) continue;
+            const float g = cb[j][k];
+            if (a.dC) a.dC[base + k] = g;
+            if (a.Cw) {
+                const float craw = a.C[base + k];   // the registers do not hold raw costs
+                if (a.rule == 0) {
+                    const float gl = -g;
+                    const float mo = a.b1 * a.mom[base + k] + (1.f - a.b1) * gl;
+                    const float ve = a.b2 * a.vel[base + k] + (1.f - a.b2) * gl * gl;
+                    a.mom[base + k] = mo;
+                    a.vel[base + k] = ve;
+                    a.Cw[base + k] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
+                } else {
+                    a.Cw[base + k] = craw + a.lr * g;
+                }
+            }
+        }
+    }
+}
+
 template <int MP, int R, bool WIDE, bool RECOMP>
 __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
@@ -1103,39 +1144,8 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     }
 
     // epilogue: write gF * dF/dC, or apply the ascent step to C in place
-    if (!active) return;
-    const int mo = opaque_u(m);
-    float bc1 = 1.f, bc2 = 1.f;
-    if (a.Cw && a.rule == 0) {
-        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
-        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
-        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int i = tm.lt + j * tm.L;
-        if (i >= I) continue;
-        const int64_t base = (u * I + i) * (int64_t)m;
-#pragma unroll
-        for (int k = 0; k < MP; ++k) {
-            if (k >= mo) continue;
-            const float g = cb[j][k];
-            if (a.dC) a.dC[base + k] = g;
-            if (a.Cw) {
-                const float craw = a.C[base + k];   // the registers hold centred scaled costs
-                if (a.rule == 0) {
-                    const float gl = -g;
-                    const float mo = a.b1 * a.mom[base + k] + (1.f - a.b1) * gl;
-                    const float ve = a.b2 * a.vel[base + k] + (1.f - a.b2) * gl * gl;
-                    a.mom[base + k] = mo;
-                    a.vel[base + k] = ve;
-                    a.Cw[base + k] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
-                } else {
-                    a.Cw[base + k] = craw + a.lr * g;
-                }
-            }
-        }
-    }
+    if (active) bwd_epilogue<MP, R>(a, cb, u, tm);
+
 }
 
 // ---------------------------------------------------------------------------
@@ -1407,6 +1417,325 @@ __device__ __forceinline__ void ibwd_body(const BwdArgs& a, int64_t u_first, flo
 }
 
 // ---------------------------------------------------------------------------
+// Reverse sweep in the scaling form (every iterate stored, K = 1).  The
+// registers hold Kt_ik = 2^(a_ik + rf_k + ph_i) for reference column
+// potentials rf and a row offset ph that puts each row's largest entry at 1,
+// so that P^t_ik = Kt_ik w_k / s_i with w_k = 2^(gamma^{t-1}_k - rf_k) (one
+// exponential per column and iteration) and s_i = sum_k Kt_ik w_k: the
+// reverse recursion of the log-domain sweep runs on multiplies and
+// multiply-adds only.  When a live column's w leaves [2^-32, 2^32] (or every
+// `absorb` iterations, if set) the reference moves to gamma^{t-1} and Kt is
+// rebuilt from the costs in HBM, one exponential per cell; entries that
+// underflow at a rebuild stay below 2^-94 of their row until the next one.
+
+// Kt of the lane's rows for reference rf: from the centred costs held in kt
+// (FROM_REGS, at the start) or re-read from C.
+template <int MP, int R, bool FROM_REGS>
+__device__ __forceinline__ void rebase_rows(const float* C, int64_t u, const Team& tm, int I, int m,
+                                            float c2, const float (&om)[R], const float (&off)[R],
+                                            const float (&rf)[MP], float (&kt)[R][MP]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        const bool valid = om[j] > 0.f;
+        const float* src = C + (u * I + (valid ? i : 0)) * (int64_t)m;
+        float z[MP];
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            float a0;
+            if constexpr (FROM_REGS)
+                a0 = kt[j][k];
+            else
+                a0 = valid ? fmaf(src[k < m ? k : m - 1], c2, -off[j]) : 0.f;
+            z[k] = a0 + rf[k];
+        }
+        const float M = Tree<MP>::max(z);
+#pragma unroll
+        for (int k = 0; k < MP; ++k) kt[j][k] = ex2(z[k] - M);
+    }
+}
+
+// Start of the reverse sweep in the scaling form (see rev_init).
+template <int MP, int R, bool WIDE>
+__device__ __forceinline__ void rev_init_s(const BwdArgs& a, const float (&kt)[R][MP],
+                                           const float (&om)[R], const float (&wv)[MP],
+                                           const float (&rho)[MP], const float (&rg)[R],
+                                           float (&fb0)[R], float (&cb)[R][MP],
+                                           float (&acc)[WIDE ? 1 : MP], float (&q)[n_slots(MP)],
+                                           int64_t u, bool active, const Team& tm) {
+    const int m = opaque_u(a.m);
+    float ek[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) ek[k] = (k < m - 1) ? a.e[k] : 0.f;
+    float w[R], xe[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float ps[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MP; ++k) ps[k & 3] = fmaf(kt[j][k], wv[k], ps[k & 3]);
+        w[j] = om[j] * rcp((ps[0] + ps[1]) + (ps[2] + ps[3])) * a.inv_eps;
+        fb0[j] = 0.f;
+        xe[j] = 0.f;
+    }
+    for_chunks<MP>([&](auto ch) {
+        constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+        float v[ci.n];
+#pragma unroll
+        for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) {
+                const int k = ci.k0 + kk;
+                const float xs = fmaf(kt[j][k], wv[k], 0.f) * w[j] * rho[k];   // x / eps
+                const float gx = rg[j] * ek[k] * xs;                            // G x / eps
+                cb[j][k] = -gx;
+                fb0[j] += gx;
+                v[kk] += gx;
+                xe[j] = fmaf(ek[k], xs, xe[j]);
+            }
+        }
+        if constexpr (WIDE) {
+            scatter_chunk<MP, decltype(ch)::value>(v, q);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) acc[ci.k0 + kk] = v[kk];
+        }
+    });
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        if (a.dr && active && i < a.I)
+            a.dr[u * a.I + i] = (float)(a.gF / a.imp[i]) * (xe[j] / a.inv_eps);
+    }
+}
+
+// Reverse of iteration t in the scaling form, one row of e = Kt w kept at a
+// time (see rev_pass).
+template <int MP, int R>
+__device__ __forceinline__ void rev_pass_s(const float (&kt)[R][MP], const float (&om)[R],
+                                           const float (&wv)[MP], const float (&gh)[MP],
+                                           const float (&fb0)[R], bool first, float (&cb)[R][MP],
+                                           float (&acc)[MP]) {
+#pragma unroll
+    for (int k = 0; k < MP; ++k) acc[k] = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float e[MP];
+#pragma unroll
+        for (int k = 0; k < MP; ++k) e[k] = kt[j][k] * wv[k];
+        const float s = Tree<MP>::sum(e);
+        float pd[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MP; ++k) pd[k & 3] = fmaf(e[k], gh[k], pd[k & 3]);
+        const float d = (pd[0] + pd[1]) + (pd[2] + pd[3]);
+        const float w = om[j] * rcp(s);
+        const float fb = (first ? fb0[j] : 0.f) - w * d;
+        const float aa = w * fb;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            cb[j][k] = fmaf(e[k], fmaf(w, gh[k], aa), cb[j][k]);
+            acc[k] = fmaf(e[k], aa, acc[k]);
+        }
+    }
+}
+
+// Two-pass variant (wide teams whose registers cannot keep a row of e): row
+// totals first, then the cost adjoint and the column partials chunk by chunk.
+// The second pass forms e as an FMA with 0 so that the first pass's products
+// are not kept live for it.
+template <int MP, int R>
+__device__ __forceinline__ void rev_pass_s_recomp(const float (&kt)[R][MP], const float (&om)[R],
+                                                  const float (&wv)[MP], const float (&gh)[MP],
+                                                  const float (&fb0)[R], bool first,
+                                                  float (&cb)[R][MP], float (&q)[n_slots(MP)]) {
+    float w[R], aa[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        float ps[4] = {0.f, 0.f, 0.f, 0.f}, pd[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            const float e = kt[j][k] * wv[k];
+            ps[k & 3] += e;
+            pd[k & 3] = fmaf(e, gh[k], pd[k & 3]);
+        }
+        const float s = (ps[0] + ps[1]) + (ps[2] + ps[3]);
+        const float d = (pd[0] + pd[1]) + (pd[2] + pd[3]);
+        w[j] = om[j] * rcp(s);
+        const float fb = (first ? fb0[j] : 0.f) - w[j] * d;
+        aa[j] = w[j] * fb;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    for_chunks<MP>([&](auto ch) {
+        constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+        float v[ci.n];
+#pragma unroll
+        for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+#pragma unroll
+            for (int kk = 0; kk < ci.n; ++kk) {
+                const int k = ci.k0 + kk;
+                const float e = fmaf(kt[j][k], wv[k], 0.f);
+                cb[j][k] = fmaf(e, fmaf(w[j], gh[k], aa[j]), cb[j][k]);
+                v[kk] = fmaf(e, aa[j], v[kk]);
+            }
+        }
+        scatter_chunk<MP, decltype(ch)::value>(v, q);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int MP, int R, bool WIDE, bool RECOMP>
+__device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, float* smem) {
+    const Team tm = make_team(a.L);
+    const int teams = blockDim.x / a.L;
+    const int64_t u = u_first + tm.team;
+    const bool active = tm.team < teams && u < a.U;
+    const int I = a.I, m = a.m;
+    constexpr int BL = kLoadBlock;
+    float* seg = smem + tm.team * ((BL + 1) * MP);
+    float* red = smem + teams * ((BL + 1) * MP) + tm.team * (2 * tm.W * MP);
+
+    float kt[R][MP], om[R], off[R];
+    load_costs<MP, R>(a.C, u, active, tm, I, m, a.c2, kt, om, off);   // centred costs until the first rebase
+
+    float rg[R];   // gF r_i / Imp_i, so that G_ik = rg_i e_k
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tm.lt + j * tm.L;
+        rg[j] = (active && i < I) ? (float)(a.gF * (double)a.r[u * I + i] / a.imp[i]) : 0.f;
+    }
+    float gdum[MP];
+    Cols<MP, WIDE> cs;
+    cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gdum);
+
+    const float* hist = active ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
+    float cb[R][MP], fb0[R];
+    float gbar[WIDE ? 1 : MP];
+#pragma unroll
+    for (int k = 0; k < (WIDE ? 1 : MP); ++k) gbar[k] = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) fb0[j] = 0.f;
+    float rf[MP];                 // reference potentials (wide: wave-uniform copies)
+#pragma unroll
+    for (int k = 0; k < MP; ++k) rf[k] = 0.f;   // set at t = T, before any use
+    [[maybe_unused]] float rfd = 0.f;   // wide: the owned column's reference
+
+    int par = 0;
+    const int nblk = (a.T + BL - 1) / BL;
+    for (int s = nblk - 1; s >= 0; --s) {
+        const int t0 = s * BL;
+        const int t1 = min(t0 + BL, a.T);
+        const int n = t1 - t0;
+        __syncthreads();  // the previous block's reads of seg are complete
+        for (int idx = tm.lt; idx < (n + 1) * MP; idx += tm.L) {
+            const int qq = idx / MP, k = idx - qq * MP;
+            seg[idx] = active ? hist[(int64_t)(t0 + qq) * a.hs + k] : 0.f;
+        }
+        __syncthreads();
+
+        for (int qq = n; qq >= 1; --qq) {
+            const int t = t0 + qq;
+            const float* sq = seg + qq * MP;        // gamma^t
+            const float* sp = seg + (qq - 1) * MP;  // gamma^{t-1}
+            const bool force = t == a.T || (a.absorb > 0 && (a.T - t) % a.absorb == 0);
+
+            // scalings of gamma^{t-1} against the reference; rebase when out of range
+            float wv[MP];
+            if constexpr (WIDE) {
+                const float gpd = (cs.col >= 0) ? sp[cs.col] : kNeg;
+                float wd = cs.live ? ex2(gpd - rfd) : 0.f;
+                const bool bad = wave_any(cs.live && !(wd >= kScaleLo && wd <= kScaleHi));
+                if (force || bad) {
+                    rfd = gpd;
+                    wd = cs.live ? 1.f : 0.f;
+                    spread_owned<MP>(rfd, rf);
+                    if (t == a.T)
+                        rebase_rows<MP, R, true>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                    else
+                        rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                }
+                spread_owned<MP>(wd, wv);
+            } else {
+                bool bad = false;
+#pragma unroll
+                for (int k = 0; k < MP; ++k) {
+                    wv[k] = ex2(sp[k] - rf[k]);   // padding: kNeg - kNeg = 0, w = 1 on a zero Kt
+                    bad = bad || !(wv[k] >= kScaleLo && wv[k] <= kScaleHi);
+                }
+                if (force || wave_any(bad)) {
+#pragma unroll
+                    for (int k = 0; k < MP; ++k) {
+                        rf[k] = sp[k];
+                        wv[k] = 1.f;
+                    }
+                    if (t == a.T)
+                        rebase_rows<MP, R, true>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                    else
+                        rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                }
+            }
+
+            if (t == a.T) {
+                float rho[MP];
+                float gp[MP];
+                if constexpr (WIDE) {
+                    spread_owned<MP>((cs.col >= 0) ? sp[cs.col] : kNeg, gp);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < MP; ++k) gp[k] = sp[k];
+                }
+#pragma unroll
+                for (int k = 0; k < MP; ++k) rho[k] = ex2(sq[k] - gp[k]);   // 1 on padding
+                float acc[WIDE ? 1 : MP];
+                float q[n_slots(MP)];
+                rev_init_s<MP, R, WIDE>(a, kt, om, wv, rho, rg, fb0, cb, acc, q, u, active, tm);
+                if constexpr (WIDE) {
+                    gbar[0] = wide_total<MP>(q, tm, cs.col, red, par);
+                } else {
+                    group_allreduce<MP>(acc, tm.L);
+#pragma unroll
+                    for (int k = 0; k < MP; ++k) gbar[k] = acc[k];
+                }
+                par ^= 1;
+            }
+
+            // gh_k = gbar_k / sig^t_k
+            float gh[MP];
+            if constexpr (WIDE) {
+                const float ghd = cs.live ? gbar[0] * ex2(sq[cs.col] - sp[cs.col]) * cs.ibc : 0.f;
+                spread_owned<MP>(ghd, gh);
+            } else {
+#pragma unroll
+                for (int k = 0; k < MP; ++k) gh[k] = gbar[k] * ex2(sq[k] - sp[k]) * cs.ib[k];
+            }
+
+            // reverse of iteration t
+            if constexpr (WIDE) {
+                float q[n_slots(MP)];
+                if constexpr (RECOMP) {
+                    rev_pass_s_recomp<MP, R>(kt, om, wv, gh, fb0, t == a.T, cb, q);
+                } else {
+                    float acc[MP];
+                    rev_pass_s<MP, R>(kt, om, wv, gh, fb0, t == a.T, cb, acc);
+                    scatter_all<MP>(acc, q);
+                }
+                gbar[0] = -wide_total<MP>(q, tm, cs.col, red, par);
+            } else {
+                float acc[MP];
+                rev_pass_s<MP, R>(kt, om, wv, gh, fb0, t == a.T, cb, acc);
+                group_allreduce<MP>(acc, tm.L);
+#pragma unroll
+                for (int k = 0; k < MP; ++k) gbar[k] = -acc[k];
+            }
+            par ^= 1;
+        }
+    }
+    if (active) bwd_epilogue<MP, R>(a, cb, u, tm);
+}
+
+// ---------------------------------------------------------------------------
 // Per-lane registers available at launch bound LB (512 per SIMD lane shared
 // by LB / 256 waves, at most 256 architectural VGPRs), minus a reserve for
 // addresses and temporaries.
@@ -1422,6 +1751,16 @@ __global__ __launch_bounds__(LB) void k_fwd(FwdArgs a) {
     if (a.stop && *a.stop) return;   // the outer loop has ended
     fwd_body<MP, R, WIDE, recomp_fwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
                                                      smem);
+}
+
+// Scaling-form reverse sweep (K = 1; same gradient as k_bwd).  Its register
+// need is the log-domain kernel's, so it recomputes under the same rule.
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_bwds(BwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    bwds_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
+                                                      smem);
 }
 
 // Scaling-form forward (same iterates as k_fwd).
@@ -1481,7 +1820,7 @@ __global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
     }
 }
 
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 __global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
                                               const BatchItem* __restrict__ items, int n_items,
                                               unsigned* counter) {
@@ -1495,7 +1834,10 @@ __global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
         if (it >= n_items) break;
         const BatchItem bi = items[it];
         const BwdArgs a = descs[bi.inst];
-        bwd_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
+        if constexpr (SCALE)
+            bwds_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
+        else
+            bwd_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
     }
 }
 
@@ -1505,10 +1847,11 @@ void launch_bfwd(const FwdArgs* d, const BatchItem* it, int n, unsigned* ctr, in
     hipLaunchKernelGGL((k_bfwd<MP, R, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
                        ctr);
 }
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 void launch_bbwd(const BwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bbwd<MP, R, WIDE>), dim3(grid), dim3(block), lds, s, d, it, n, ctr);
+    hipLaunchKernelGGL((k_bbwd<MP, R, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
+                       ctr);
 }
 template <int MP, int R, bool WIDE, bool SCALE>
 int occupancy_bfwd(int block, size_t lds) {
@@ -1518,10 +1861,10 @@ int occupancy_bfwd(int block, size_t lds) {
         return 1;
     return n > 0 ? n : 1;
 }
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, bool SCALE>
 int occupancy_bbwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, WIDE>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, WIDE, SCALE>, block, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
@@ -1534,6 +1877,10 @@ void launch_fwd(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s
 template <int MP, int R, int LB, bool WIDE>
 void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_bwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
+}
+template <int MP, int R, int LB, bool WIDE>
+void launch_bwds(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_bwds<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
 template <int MP, int R, int LB, bool WIDE>
 void launch_fwds(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
@@ -1563,17 +1910,20 @@ constexpr FusedEntry entry() {
                           &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_fwds<FR_MP, R, LB, WIDE>,
                           &launch_bfwd<FR_MP, R, WIDE, false>,
-                          &launch_bbwd<FR_MP, R, WIDE>,
+                          &launch_bbwd<FR_MP, R, WIDE, false>,
                           &occupancy_bfwd<FR_MP, R, WIDE, false>,
-                          &occupancy_bbwd<FR_MP, R, WIDE>,
+                          &occupancy_bbwd<FR_MP, R, WIDE, false>,
                           &launch_bfwd<FR_MP, R, WIDE, true>,
-                          &occupancy_bfwd<FR_MP, R, WIDE, true>};
+                          &occupancy_bfwd<FR_MP, R, WIDE, true>,
+                          &launch_bwds<FR_MP, R, LB, WIDE>,
+                          &launch_bbwd<FR_MP, R, WIDE, true>,
+                          &occupancy_bbwd<FR_MP, R, WIDE, true>};
     } else {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,
                           &launch_fwdc<FR_MP, R, LB, WIDE>, &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_fwds<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, nullptr};
+                          nullptr, nullptr, &launch_bwds<FR_MP, R, LB, WIDE>, nullptr, nullptr};
     }
 }
 

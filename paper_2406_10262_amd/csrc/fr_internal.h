@@ -60,6 +60,7 @@ struct BwdArgs {
     const float* gw;          // implicit form: converged column potentials [U][hs]
     const float* phi;         // implicit form: row potentials [U][I]
     int cg_max;               // implicit form: conjugate-gradient iteration cap
+    int absorb;               // scaling-form sweep: also rebase every `absorb` iterations
     float cg_tol;             // implicit form: relative residual to stop at
     int64_t step_const;
     double gF;
@@ -99,6 +100,9 @@ struct FusedEntry {
     Occupancy occ_bbwd;
     BFwdLaunch bfwds;   // batched scaling-form forward
     Occupancy occ_bfwds;
+    BwdLaunch bwds;     // scaling-form reverse sweep (K = 1)
+    BBwdLaunch bbwds;   // batched scaling-form reverse sweep (K = 1)
+    Occupancy occ_bbwds;
 };
 
 // Instantiated column classes.  Each class is compiled in its own translation

@@ -16,8 +16,8 @@ import torch
 
 import oracle
 import workloads as W
-from gpu_util import (F_REL, IMP_REL, X_ABS, assert_step_close, device_problem, f_err,
-                      oracle_step)
+from gpu_util import (F_REL, GRAD_REL, IMP_REL, X_ABS, assert_step_close, device_problem,
+                      f_err, oracle_step)
 from test_gpu_forward import SHAPES
 
 pytestmark = pytest.mark.gpu
@@ -152,3 +152,30 @@ def test_form_validation(fr, ctx):
     lib = fr.load()
     assert lib.fr_ctx_set_form(ctx.handle, 7, 0) == 3
     assert lib.fr_ctx_set_form(None, 0, 0) == 1
+
+
+@pytest.mark.parametrize("absorb", [0, 1, 6])
+@pytest.mark.parametrize("U,I,m,L,R", [(37, 23, 5, 8, 3), (5, 100, 10, 64, 2), (6, 100, 10, 128, 1),
+                                       (3, 300, 20, 128, 3), (2, 257, 13, 64, 6)])
+def test_scaling_reverse_sweep_matches_oracle(fr, ctx, U, I, m, L, R, absorb):
+    """The reverse sweep in the scaling form (K = 1), its reference rebased on
+    the range test alone, every iteration, or every sixth, against the oracle's
+    reverse mode."""
+    inst = W.small_instance(U, I, m, seed=U + 7 * I + m, eps=0.05, T=40)
+    C = W.random_costs(U, I, m, 0.1, seed=3 * I + m)
+    print(f"case scaling backward U={U} I={I} m={m} L={L} R={R} absorb={absorb}", flush=True)
+    ctx.set_form("scaling", absorb)
+    try:
+        ctx.set_launch(I, m, L, R)
+    except fr.FairRankError as ex:
+        if ex.code == 8:
+            pytest.skip(f"launch ({L},{R}) not instantiated for m={m}")
+        raise
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    Cd = torch.from_numpy(C).cuda()
+    out = fr.step(ctx, prob, Cd)
+    dC, dr = fr.backward(ctx, prob, Cd, out["imp"], 1.0, K=1)
+    gC, gr = oracle.grad(inst.r, inst.e, float(inst.eps), inst.T, C)
+    scale = np.max(np.abs(gC))
+    assert np.max(np.abs(dC.double().cpu().numpy() - gC)) <= GRAD_REL * scale
+    assert np.max(np.abs(dr.double().cpu().numpy() - gr)) <= 1e-5 * np.max(np.abs(gr))
