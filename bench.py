@@ -44,7 +44,11 @@ import numpy as np  # noqa: E402
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 PEAK_SLOTS = CUS * SIMDS * LANES * CLOCK          # 3.93e13 lane-slots/s
 FWD_SLOTS = {"log": 5, "scaling": 2}   # scaling form: the two multiply-adds of u and v
-BWD_SLOTS = 8
+# reverse sweep: log domain 8 (the forward's 5 plus the row dot product and the two
+# accumulations); scaling form 6 (the product K w, the row-sum add, and four
+# multiply-adds: row dot product, cost adjoint (two), column partial)
+BWD_SLOTS = {"log": 8, "scaling": 6}
+FORMS = {0: "log", 1: "scaling"}
 HBM_PEAK = 8.0e12
 
 
@@ -73,6 +77,9 @@ def load_traffic(kernel, cfg):
 def _lib_timing(lib):
     lib.fr_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.fr_ctx_kernel_times.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+    lib.fr_ctx_kernel_forms.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p]
 
 
 def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
@@ -90,9 +97,14 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
     lib.fr_ctx_set_timing(ctx.handle, 0)
     cells = prob.U * prob.I * prob.m
     per_launch = cells * (prob.T + 1)   # cell-iterations of one launch (incl. plan / init pass)
-    fk = "k_fwds" if form == "scaling" else "k_fwd"
-    ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS[form]),
-          "k_bwd": (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS)}
+    ff, bf = ctypes.c_int32(), ctypes.c_int32()
+    lib.fr_ctx_kernel_forms(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(ff),
+                            ctypes.byref(bf))
+    fform, bform = FORMS[ff.value], FORMS[bf.value]
+    fk = "k_fwds" if fform == "scaling" else "k_fwd"
+    bk = "k_bwds" if bform == "scaling" else "k_bwd"
+    ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS[fform]),
+          bk: (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS[bform])}
     kernels = {k: {"avg_ms": v[0], "launches": v[1],
                    "cell_iters_per_s": per_launch / (v[0] * 1e-3),
                    "alg_slots_per_cell_iter": v[2],
@@ -105,10 +117,11 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
             "peak": PEAK_SLOTS / 1e12, "unit": "T VALU lane-slots/s",
             "frac": achieved / PEAK_SLOTS, "traffic": load_traffic(dom, cfg_name),
             "avg_launch_ms": avg_ms,
-            "model": f"{slots} non-transcendental VALU lane-slots per cell-iteration (the "
-                     "exponential overlaps on its own half-rate pipe), U*I*m*(T+1) "
-                     "cell-iterations per launch; peak = 256 CUs x 64 lanes x 2.4 GHz"}
-    print(f"bench: kernels ({form} forward) fwd {ks[fk][0]:.3f} ms bwd {ks['k_bwd'][0]:.3f} ms "
+            "model": f"{slots} algorithmic VALU lane-slots per cell-iteration of the {dom} "
+                     "arithmetic (log domain: non-transcendental slots, the exponential "
+                     "overlapping on its own pipe), U*I*m*(T+1) cell-iterations per launch; "
+                     "peak = 256 CUs x 64 lanes x 2.4 GHz"}
+    print(f"bench: kernels ({form} form) {fk} {ks[fk][0]:.3f} ms {bk} {ks[bk][0]:.3f} ms "
           "per launch", flush=True)
     return kernels, roof
 
@@ -238,10 +251,11 @@ def bench_solve(args, fr, lib, dev, name):
               "cells": cells, "cell_iters_per_step": work}
     out = base_record(args, value, ms_per_step, config)
     out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics,
-                "log_domain_forward": {
-                    "k_fwd": kernels_log["k_fwd"],
-                    "note": "the same iterates with one exponential per cell-iteration; the "
-                            "solve above runs the scaling form (k_fwds)"}})
+                "log_domain_kernels": {
+                    **kernels_log,
+                    "note": "the same iterates and gradient in log-domain arithmetic (one "
+                            "exponential per cell-iteration); the solve above runs the "
+                            "scaling form where it applies"}})
     if name != "C5" and not args.skip_extras:
         out["converged_map"] = bench_converged(fr, ctx, prob, N, lr, Fh[-1])
         out["baselines"] = bench_baselines(fr, ctx, prob)

@@ -24,6 +24,13 @@ fr_status fr_ctx_set_timing(fr_ctx* ctx, int enable);
 fr_status fr_ctx_kernel_times(fr_ctx* ctx, double* fwd_ms, int64_t* fwd_launches,
                               double* bwd_ms, int64_t* bwd_launches);
 
+/* The arithmetic form (FR_FORM_LOG or FR_FORM_SCALING) of the fused forward
+ * and reverse sweep that fr_solve runs on this context for a problem of this
+ * shape with checkpoint interval K (0 = every iterate), at the launch shape
+ * fr_get_launch reports.  Host pointers, each optional. */
+fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
+                              int32_t checkpoint_every, int32_t* fwd_form, int32_t* bwd_form);
+
 /* ALU microbenchmark on the current device, default stream, synchronous:
  * kind 0 = dependent chains of v_exp_f32, 1 = chains of FP32 FMA, 2 = one
  * exponential followed by five FMAs.  `blocks` blocks of 256 threads, each

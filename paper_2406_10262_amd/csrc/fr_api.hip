@@ -1052,6 +1052,19 @@ fr_status fr_ctx_set_form(fr_ctx* ctx, int32_t form, int32_t absorb_every) {
     return FR_OK;
 }
 
+fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
+                              int32_t checkpoint_every, int32_t* fwd_form, int32_t* bwd_form) {
+    if (!ctx) return FR_E_NULL;
+    if (n_users < 1 || n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems)
+        return FR_E_SHAPE;
+    Shape sh;
+    fr_status st = make_shape(ctx, n_users, n_items, m, resolve_k(checkpoint_every), &sh);
+    if (st) return st;
+    if (fwd_form) *fwd_form = (sh.fwd == sh.fe->fwds) ? FR_FORM_SCALING : FR_FORM_LOG;
+    if (bwd_form) *bwd_form = (sh.bwd == sh.fe->bwds) ? FR_FORM_SCALING : FR_FORM_LOG;
+    return FR_OK;
+}
+
 fr_status fr_ctx_set_timing(fr_ctx* ctx, int enable) {
     if (!ctx) return FR_E_NULL;
     ctx->timing = enable != 0;
