@@ -1429,7 +1429,9 @@ __device__ __forceinline__ void ibwd_body(const BwdArgs& a, int64_t u_first, flo
 // underflow at a rebuild stay below 2^-94 of their row until the next one.
 
 // Kt of the lane's rows for reference rf: from the centred costs held in kt
-// (FROM_REGS, at the start) or re-read from C.
+// (FROM_REGS, at the start) or re-read from C -- then in two passes over the
+// row (its maximum, then the exponentials), so that no row of temporaries is
+// live beside Kt and the cost adjoints.
 template <int MP, int R, bool FROM_REGS>
 __device__ __forceinline__ void rebase_rows(const float* C, int64_t u, const Team& tm, int I, int m,
                                             float c2, const float (&om)[R], const float (&off)[R],
@@ -1439,19 +1441,18 @@ __device__ __forceinline__ void rebase_rows(const float* C, int64_t u, const Tea
         const int i = tm.lt + j * tm.L;
         const bool valid = om[j] > 0.f;
         const float* src = C + (u * I + (valid ? i : 0)) * (int64_t)m;
-        float z[MP];
-#pragma unroll
-        for (int k = 0; k < MP; ++k) {
-            float a0;
+        auto z = [&](int k) {
             if constexpr (FROM_REGS)
-                a0 = kt[j][k];
+                return kt[j][k] + rf[k];
             else
-                a0 = valid ? fmaf(src[k < m ? k : m - 1], c2, -off[j]) : 0.f;
-            z[k] = a0 + rf[k];
-        }
-        const float M = Tree<MP>::max(z);
+                return (valid ? fmaf(src[k < m ? k : m - 1], c2, -off[j]) : 0.f) + rf[k];
+        };
+        float mx[4] = {kNeg, kNeg, kNeg, kNeg};
 #pragma unroll
-        for (int k = 0; k < MP; ++k) kt[j][k] = ex2(z[k] - M);
+        for (int k = 0; k < MP; ++k) mx[k & 3] = fmaxf(mx[k & 3], z(k));
+        const float M = fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3]));
+#pragma unroll
+        for (int k = 0; k < MP; ++k) kt[j][k] = ex2(z(k) - M);
     }
 }
 
@@ -1622,6 +1623,19 @@ __device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, flo
     for (int k = 0; k < MP; ++k) rf[k] = 0.f;   // set at t = T, before any use
     [[maybe_unused]] float rfd = 0.f;   // wide: the owned column's reference
 
+    // first reference: gamma^{T-1}, from the centred costs in the registers
+    {
+        const float* last = active ? hist + (int64_t)(a.T - 1) * a.hs : nullptr;
+        if constexpr (WIDE) {
+            rfd = (active && cs.col >= 0) ? last[cs.col] : 0.f;
+            spread_owned<MP>(rfd, rf);
+        } else {
+#pragma unroll
+            for (int k = 0; k < MP; ++k) rf[k] = active ? last[k] : 0.f;
+        }
+        rebase_rows<MP, R, true>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+    }
+
     int par = 0;
     const int nblk = (a.T + BL - 1) / BL;
     for (int s = nblk - 1; s >= 0; --s) {
@@ -1639,7 +1653,7 @@ __device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, flo
             const int t = t0 + qq;
             const float* sq = seg + qq * MP;        // gamma^t
             const float* sp = seg + (qq - 1) * MP;  // gamma^{t-1}
-            const bool force = t == a.T || (a.absorb > 0 && (a.T - t) % a.absorb == 0);
+            const bool force = t < a.T && a.absorb > 0 && (a.T - t) % a.absorb == 0;
 
             // scalings of gamma^{t-1} against the reference; rebase when out of range
             float wv[MP];
@@ -1651,10 +1665,7 @@ __device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, flo
                     rfd = gpd;
                     wd = cs.live ? 1.f : 0.f;
                     spread_owned<MP>(rfd, rf);
-                    if (t == a.T)
-                        rebase_rows<MP, R, true>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
-                    else
-                        rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                    rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
                 }
                 spread_owned<MP>(wd, wv);
             } else {
@@ -1670,10 +1681,7 @@ __device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, flo
                         rf[k] = sp[k];
                         wv[k] = 1.f;
                     }
-                    if (t == a.T)
-                        rebase_rows<MP, R, true>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
-                    else
-                        rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
+                    rebase_rows<MP, R, false>(a.C, active ? u : 0, tm, I, m, a.c2, om, off, rf, kt);
                 }
             }
 
