@@ -37,7 +37,12 @@
  *     a flag word in the workspace; fr_solve reports them (it synchronises),
  *     after the asynchronous calls fr_sync_status does.
  *   * Sizes: 1 <= U, 2 <= m <= I (the dummy mass I-m+1 must be >= 1),
- *     m <= 64, I <= 4096, eps > 0 finite, T >= 1.
+ *     m <= 64, I <= 4096, eps > 0 finite, T >= 1 (FR_E_SHAPE / FR_E_PARAM
+ *     outside).  The fused kernels hold a consumer's plan in the registers
+ *     of at most 1024 lanes, which covers I <= 4096 for m <= 32 and
+ *     I <= 2048 for 32 < m <= 64; larger plans get FR_E_UNSUPPORTED from the
+ *     solver entry points (the plain form, fr_nsw, fr_metrics and the
+ *     baselines take every valid size).
  */
 #ifndef FAIRRANK_H
 #define FAIRRANK_H

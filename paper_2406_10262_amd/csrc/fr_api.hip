@@ -133,7 +133,7 @@ std::pair<int, int> default_launch(int64_t U, int I, int m) {
     const Registry& reg = registry();
     const int mp = reg.mp_for(m);
     double best = 1e300;
-    std::pair<int, int> out{64, 1};
+    std::pair<int, int> out{0, 0};   // stays {0, 0} if no instantiated kernel holds I rows
     const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 576, 640, 704,
                       768, 832, 896, 960, 1024};
     for (int L : Ls) {
@@ -162,6 +162,7 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     auto it = ctx->launch.find({I, m});
     lr = (it != ctx->launch.end()) ? it->second : default_launch(U, I, m);
     const int L = lr.first, R = lr.second;
+    if (L == 0) return FR_E_UNSUPPORTED;   // more rows than any instantiated kernel holds
     if (!lanes_ok(L) || (int64_t)L * R < I) return FR_E_PARAM;
     int block = block_for(L);
     const FusedEntry* fe = reg.pick(mp, R, L, block);
@@ -656,6 +657,7 @@ fr_status fr_get_launch(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m
     if (n_users < 1) return FR_E_SHAPE;
     std::pair<int, int> lr =
         (it != ctx->launch.end()) ? it->second : default_launch(n_users, n_items, m);
+    if (lr.first == 0) return FR_E_UNSUPPORTED;
     *lanes = lr.first;
     *rows = lr.second;
     return FR_OK;
