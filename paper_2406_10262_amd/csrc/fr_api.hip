@@ -714,8 +714,8 @@ fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_
 
 // ---------------------------------------------------------------- metrics
 struct MetricsLayout {
-    size_t hdr, W, partial, rsum, pmax, diag, total;
-    int nchunk, tiles;
+    size_t hdr, W, partial, rsum, pmax, diag, epart, total;
+    int nchunk, tiles, splits;
 };
 
 MetricsLayout metrics_layout(const fr_problem* p) {
@@ -737,6 +737,9 @@ MetricsLayout metrics_layout(const fr_problem* p) {
     off += align_up(sizeof(double) * (size_t)I * L.tiles);
     L.diag = off;
     off += align_up(sizeof(double) * I);
+    L.splits = metrics_splits(U, I);
+    L.epart = off;
+    if (L.splits > 1) off += align_up(sizeof(double) * (size_t)L.splits * I * I);
     L.total = off;
     return L;
 }
@@ -770,6 +773,8 @@ fr_status fr_metrics(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtyp
     b.rsum = (double*)(w + Lw.rsum);
     b.pmax = (double*)(w + Lw.pmax);
     b.diag = (double*)(w + Lw.diag);
+    b.epart = (double*)(w + Lw.epart);
+    b.splits = Lw.splits;
     launch_metrics(X, x_dtype == FR_BF16, prob->r, prob->e, prob->n_users, prob->n_items, prob->m,
                    b, out, envy, imp, s);
     FR_TRY(hipGetLastError());

@@ -158,8 +158,11 @@ struct MetricsBufs {
     double* pmax;       // [I][tiles] row maxima of E per column tile
     double* diag;       // [I] E_ii
     WsHeader* hdr;      // scratch header for the reduction
+    double* epart;      // [splits][I][I] partial E when the consumers are split
+    int splits;
 };
 int metrics_tiles(int I);
+int metrics_splits(int64_t U, int I);
 void launch_metrics(const void* X, int x_bf16, const float* r, const float* e, int64_t U, int I,
                     int m, const MetricsBufs& b, double* out, double* envy, double* imp,
                     hipStream_t s);

@@ -85,3 +85,15 @@ def test_uniform_policy_on_gpu(fr):
     X = np.broadcast_to((b / I).astype(np.float32), (U, I, m)).copy()
     out = _check(fr, r, e, torch.from_numpy(X).cuda(), X.astype(np.float64))
     assert out[2] == 0.0 and out[3] == 0.0
+
+
+def test_plan_not_aligned_to_16_bytes(fr):
+    """A plan that starts mid-allocation (a view one consumer in, 37 * 6 * 4 =
+    888 bytes, not a multiple of 16) takes the element-wise staging path."""
+    print("case metrics unaligned plan", flush=True)
+    U, I, m = 41, 37, 6
+    r, e, X = _case(U, I, m, seed=17, scale=0.5)
+    Xd = torch.from_numpy(X).cuda()
+    view = Xd[1:]
+    assert view.data_ptr() % 16 != 0
+    _check(fr, np.ascontiguousarray(r[1:]), e, view, X[1:].astype(np.float64))
