@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fairrank.h")
+DIAG_HEADER = os.path.join(ROOT, "include", "fairrank_diag.h")
 
 
 @pytest.fixture(scope="module")
@@ -22,8 +23,8 @@ def lib():
     return fr.load()
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(path=HEADER):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:fr_status|void|const char\*|size_t)\s+(fr_\w+)\s*\(",
                                  src, flags=re.M)))
@@ -41,7 +42,9 @@ def test_library_exports_every_declared_symbol(lib):
     out = subprocess.run(["nm", "-D", "--defined-only", fr.library_path()], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r"\bT\s+(fr_\w+)", out))
-    for n in declared_functions():
+    names = declared_functions() + declared_functions(DIAG_HEADER)
+    assert "fr_ctx_kernel_forms" in names and "fr_rank_greedy" in names
+    for n in names:
         assert n in exported, n
         assert hasattr(lib, n)
 
@@ -158,3 +161,16 @@ def test_converged_map_form_validation(lib):
         assert lib.fr_workspace_bytes(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n1)) == 3
     assert lib.fr_grad_converged(None, ctypes.byref(p), 1, 1e-4, 0, 1.0, None, None, 1, None, 1,
                                  10**9, None) == 1
+
+
+def test_newer_entry_points_reject_null_context(lib):
+    import paper_2406_10262_amd as fr
+    p = _prob(fr)
+    assert lib.fr_ctx_set_form(None, 0, 0) == 1
+    assert lib.fr_rank_maxrele(None, ctypes.byref(p), 1, None, 0, None) == 1
+    assert lib.fr_rank_greedy(None, ctypes.byref(p), 1, None, 0, None, None) == 1
+    lib.fr_ctx_kernel_forms.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+    assert lib.fr_ctx_kernel_forms(None, 10, 20, 5, 0, None, None) == 1
+    assert lib.fr_solve_progress(None, 1, None, None, None, None) == 1
