@@ -113,9 +113,14 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
     dom = max(ks, key=lambda k: ks[k][0])
     avg_ms, _, slots = ks[dom]
     achieved = per_launch * slots / (avg_ms * 1e-3)
+    traffic = load_traffic(dom, cfg_name)
     roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
             "peak": PEAK_SLOTS / 1e12, "unit": "T VALU lane-slots/s",
-            "frac": achieved / PEAK_SLOTS, "traffic": load_traffic(dom, cfg_name),
+            "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+            "hbm_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+            "hbm_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / HBM_PEAK,
+            # one outer step costs both kernels' slots per cell-iteration
+            "solve_ceiling_cell_iters_per_s": PEAK_SLOTS / (FWD_SLOTS[fform] + BWD_SLOTS[bform]),
             "avg_launch_ms": avg_ms,
             "model": f"{slots} algorithmic VALU lane-slots per cell-iteration of the {dom} "
                      "arithmetic (log domain: non-transcendental slots, the exponential "
@@ -250,6 +255,7 @@ def bench_solve(args, fr, lib, dev, name):
               "step": "one full solve (N outer steps + final forward)",
               "cells": cells, "cell_iters_per_step": work}
     out = base_record(args, value, ms_per_step, config)
+    roof["solve_frac"] = value / roof["solve_ceiling_cell_iters_per_s"]
     out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics,
                 "log_domain_kernels": {
                     **kernels_log,
