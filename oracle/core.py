@@ -11,7 +11,8 @@ C source follows the paper step by step:
                       stored iterates.
 * adam / gd        -- the ascent step of Algorithm 1 (Adam as named in
                       Section 4.1).
-* solve            -- Algorithm 1 with a fixed number of outer steps.
+* solve            -- Algorithm 1 with a fixed number of outer steps (long
+                      Adam trajectories: parity unpinned, see ``solve``).
 """
 from __future__ import annotations
 
@@ -179,7 +180,12 @@ def solve(r, e, eps, T, N, C0=None, rule="adam", lr=None, b1=0.9, b2=0.999, aeps
     """Algorithm 1 with at most N ascent steps; with grad_tol = t > 0 the loop
     ends at the first C whose gradient has ||dF/dC||_F <= t (no update there;
     the remaining F history repeats its F).  Returns dict(C, X, F_hist, imp,
-    mom, vel, gnorm (norm at each step taken, NaN after a stop), updates)."""
+    mom, vel, gnorm (norm at each step taken, NaN after a stop), updates).
+
+    Parity unpinned for long Adam runs: each step is pinned (the forward, the
+    gradient and the Adam formula separately, and the first step in closed
+    form), but a many-step Adam trajectory has no closed form or independent
+    reference; it is compared only with this oracle."""
     r, e = _d(r), _d(e)
     U, I = r.shape
     mm = e.shape[0] + 1 if m is None else m
