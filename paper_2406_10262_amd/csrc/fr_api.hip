@@ -38,6 +38,32 @@ constexpr size_t kMaxLds = 64 * 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// HIP events released on every exit path (error returns included).
+struct EventSet {
+    std::vector<hipEvent_t> ev;
+    explicit EventSet(size_t n) : ev(n, nullptr) {}
+    hipError_t create() {
+        for (auto& e : ev) {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~EventSet() {
+        for (auto e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
+// Runs f when the scope ends, however it ends.
+template <class F>
+struct OnExit {
+    F f;
+    ~OnExit() { f(); }
+};
+template <class F>
+OnExit<F> on_exit(F f) { return OnExit<F>{f}; }
+
 #define FR_TRY(expr)                                  \
     do {                                              \
         hipError_t e_ = (expr);                       \
@@ -903,8 +929,9 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     const int N = optim->outer_steps;
     if (N > 0 && ctx->timing && !tol && !conv) {
         // direct launches, each fused kernel bracketed by events
-        std::vector<hipEvent_t> ev(4 * (size_t)N);
-        for (auto& x : ev) FR_TRY(hipEventCreate(&x));
+        EventSet evs(4 * (size_t)N);
+        FR_TRY(evs.create());
+        const std::vector<hipEvent_t>& ev = evs.ev;
         for (int n = 0; n < N; ++n) {
             FR_TRY(hipEventRecord(ev[4 * n + 0], s));
             sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
@@ -926,7 +953,6 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
         }
         ctx->fwd_n += N;
         ctx->bwd_n += N;
-        for (auto& x : ev) hipEventDestroy(x);
     } else if (N > 0) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
@@ -1354,9 +1380,15 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
     if (mp < 0) return FR_E_UNSUPPORTED;
     const int I = p.n_items;
     const auto saved = ctx->launch;
-    hipEvent_t e0, e1;
-    FR_TRY(hipEventCreate(&e0));
-    FR_TRY(hipEventCreate(&e1));
+    // the candidates are tried through the context's launch cache; it is put
+    // back on every exit but a successful one, error returns included
+    bool done = false;
+    auto restore = on_exit([&] {
+        if (!done) ctx->launch = saved;
+    });
+    EventSet evs(2);
+    FR_TRY(evs.create());
+    hipEvent_t e0 = evs.ev[0], e1 = evs.ev[1];
     float best = 1e30f;
     std::pair<int, int> best_lr{0, 0};
     const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024};
@@ -1402,11 +1434,10 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    ctx->launch = saved;
     if (best_lr.first == 0) return FR_E_UNSUPPORTED;
+    ctx->launch = saved;
     ctx->launch[{I, p.m}] = best_lr;
+    done = true;
     if (lanes_out) *lanes_out = best_lr.first;
     if (rows_out) *rows_out = best_lr.second;
     return FR_OK;
