@@ -53,10 +53,16 @@ HBM_PEAK = 8.0e12
 
 
 def kernel_source_hash():
+    """Hash of the fused kernels' source with comments and white space removed
+    (a profile stays valid across comment edits, not across code changes)."""
+    import re
     h = hashlib.sha256()
     for f in ("fr_fused.hip", "fr_device.h"):
-        with open(os.path.join(ROOT, "paper_2406_10262_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2406_10262_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

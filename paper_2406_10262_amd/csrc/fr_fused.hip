@@ -19,6 +19,12 @@
 // cell.  The plan is X_ik = 2^(a_ik + gamma^T_k + phi_i), phi_i = -log2 s_i
 // from the last row half-step.
 //
+// Scaling form (k_fwds, k_bwds; see fwds_body and bwds_body).  The same
+// iterates on a register-resident kernel 2^(a + gamma_ref + phi_ref) and
+// scalings u, v (or, in the reverse sweep, w = 2^(gamma^{t-1} - gamma_ref)):
+// multiply-adds per cell, exponentials only when the scalings leave range and
+// the kernel is rebuilt from C.
+//
 // Row centring.  A constant added to a row of the costs leaves every P and X
 // unchanged (the row softmax absorbs it), so the registers hold each row of
 // scaled costs minus an offset o_i chosen to keep 2^(a + gamma) in range: the
