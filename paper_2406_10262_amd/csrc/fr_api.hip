@@ -25,6 +25,13 @@ struct fr_ctx {
     bool timing = false;                                  // per-kernel event timing
     int form = FR_FORM_SCALING;                           // Sinkhorn form of the fixed-T forward
     int absorb = 0;                                       // scaling form: forced absorption period
+    // batched solver: side streams (default priority) on which the column
+    // classes of a phase run concurrently, and the events that fork and join them
+    static constexpr int kSide = 4;
+    static constexpr int kMaxClasses = 64;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxClasses] = {};
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
 };
@@ -637,6 +644,11 @@ void fr_ctx_destroy(fr_ctx* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     if (ctx->own) hipStreamDestroy(ctx->own);
+    for (auto st : ctx->side)
+        if (st) hipStreamDestroy(st);
+    if (ctx->fork) hipEventDestroy(ctx->fork);
+    for (auto ev : ctx->join)
+        if (ev) hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -1318,21 +1330,50 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
         const Occupancy occ_b = sweep_s[c] ? P.classes[c]->occ_bbwds : P.classes[c]->occ_bbwd;
         grid_b[c] = std::max(1, std::min(nit, occ_b(256, P.lds_bwd[c]) * cus));
     }
+    // The column classes of a phase share nothing (own work lists, counters and
+    // outputs), so they run concurrently: forked from s onto the side streams
+    // and joined back (inside a capture this becomes parallel graph branches).
+    const bool fan = ncls > 1 && ncls <= fr_ctx::kMaxClasses;   // else one after another
+    if (fan && !ctx->fork) {
+        for (auto& st : ctx->side) FR_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        FR_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        for (auto& ev : ctx->join) FR_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    hipError_t perr = hipSuccess;   // first fork / join error of the phases below
+    auto keep = [&](hipError_t e) {
+        if (perr == hipSuccess) perr = e;
+    };
+    auto run_classes = [&](auto&& launch_class) {
+        if (!fan) {
+            for (int c = 0; c < ncls; ++c) launch_class(c, s);
+            return;
+        }
+        keep(hipEventRecord(ctx->fork, s));
+        for (int c = 0; c < ncls; ++c) {
+            hipStream_t sc = ctx->side[c % fr_ctx::kSide];
+            keep(hipStreamWaitEvent(sc, ctx->fork, 0));
+            launch_class(c, sc);
+            keep(hipEventRecord(ctx->join[c], sc));
+        }
+        for (int c = 0; c < ncls; ++c) keep(hipStreamWaitEvent(s, ctx->join[c], 0));
+    };
     auto forward_phase = [&](const FwdArgs* descs) {
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 0);
-        for (int c = 0; c < ncls; ++c)
+        run_classes([&](int c, hipStream_t sc) {
             (scaling ? P.classes[c]->bfwds : P.classes[c]->bfwd)(
                 descs, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_f[c], 256,
-                P.lds_fwd[c], s);
+                P.lds_fwd[c], sc);
+        });
         launch_impact_batched(drd, n_inst, dt1, (int)P.tab1.size(), dt2, (int)P.tab2.size(),
                               start_step, hdr, s);
     };
     auto backward_phase = [&]() {
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 1);
-        for (int c = 0; c < ncls; ++c)
+        run_classes([&](int c, hipStream_t sc) {
             (sweep_s[c] ? P.classes[c]->bbwds : P.classes[c]->bbwd)(
                 dba, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_b[c], 256,
-                P.lds_bwd[c], s);
+                P.lds_bwd[c], sc);
+        });
     };
 
     hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, hdr, start_step);
@@ -1345,7 +1386,10 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
         forward_phase(dfa);
         backward_phase();
         hipError_t ce = hipStreamEndCapture(s, &graph);
-        if (ce != hipSuccess) return FR_E_DEVICE;
+        if (ce != hipSuccess || perr != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return FR_E_DEVICE;
+        }
         ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (ce != hipSuccess) {
             hipGraphDestroy(graph);
@@ -1357,6 +1401,7 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
         if (ce != hipSuccess) return FR_E_DEVICE;
     }
     forward_phase(dff);
+    FR_TRY(perr);
     FR_TRY(hipGetLastError());
     return read_flags(hdr, s, false);
 }
