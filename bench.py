@@ -86,6 +86,8 @@ def _lib_timing(lib):
     lib.fr_ctx_kernel_forms.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p]
+    lib.fr_ctx_bwd_lds_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
 
 
 def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
@@ -108,7 +110,9 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
                             ctypes.byref(bf))
     fform, bform = FORMS[ff.value], FORMS[bf.value]
     fk = "k_fwds" if fform == "scaling" else "k_fwd"
-    bk = "k_bwds" if bform == "scaling" else "k_bwd"
+    nl = ctypes.c_int32()
+    lib.fr_ctx_bwd_lds_rows(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(nl))
+    bk = "k_bwds" if bform == "scaling" else ("k_bwdl" if nl.value > 0 else "k_bwd")
     ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS[fform]),
           bk: (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS[bform])}
     kernels = {k: {"avg_ms": v[0], "launches": v[1],

@@ -31,6 +31,17 @@ fr_status fr_ctx_kernel_times(fr_ctx* ctx, double* fwd_ms, int64_t* fwd_launches
 fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
                               int32_t checkpoint_every, int32_t* fwd_form, int32_t* bwd_form);
 
+/* Rows of cost adjoints per lane that the log-domain reverse sweep keeps in
+ * LDS for a problem of this shape (same arguments as fr_ctx_kernel_forms):
+ * 0 when they all stay in registers.  Teams of more than 256 lanes whose
+ * costs, cost adjoints and a pass's temporaries exceed the registers (the
+ * two-pass kernels, e.g. m = 50 with two rows per lane) keep as many of the
+ * rows of cost adjoints as fit in LDS, all but one at most, when the block's
+ * LDS allows it (the kernel then shows as k_bwdl).
+ * *rows is a host pointer. */
+fr_status fr_ctx_bwd_lds_rows(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
+                              int32_t checkpoint_every, int32_t* rows);
+
 /* ALU microbenchmark on the current device, default stream, synchronous:
  * kind 0 = dependent chains of v_exp_f32, 1 = chains of FP32 FMA, 2 = one
  * exponential followed by five FMAs.  `blocks` blocks of 256 threads, each

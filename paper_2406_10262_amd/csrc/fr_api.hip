@@ -34,6 +34,7 @@ struct fr_ctx {
     hipEvent_t join[kMaxClasses] = {};
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
+    size_t max_lds = 64 * 1024;                           // LDS a block may use on the device
 };
 
 namespace {
@@ -130,6 +131,7 @@ struct Shape {
     int absorb;
     int L, R, mp, block, teams, grid;
     size_t lds_fwd, lds_bwd;
+    size_t lds_cb;       // part of lds_bwd holding cost adjoints (reverse sweep fe->bwdl only)
 };
 
 // Issue model of one Sinkhorn iteration (forward and backward) of U consumers
@@ -215,6 +217,15 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     // two-pass (recompute) shapes spill more in that form and keep the log domain
     sh->bwd = (ctx->form == FR_FORM_SCALING && K <= 1 && fe->bwds && !fe->recomp_b) ? fe->bwds
                                                                                     : fe->bwd;
+    // wide recompute sweeps keep some rows of cost adjoints in LDS where it fits
+    sh->lds_cb = 0;
+    if (sh->bwd == fe->bwd && fe->bwdl) {
+        const size_t cb = (size_t)teams * fe->cb_rows * mp * L * sizeof(float);
+        if (teams * per_team_bwd() + cb <= ctx->max_lds) {
+            sh->bwd = fe->bwdl;
+            sh->lds_cb = cb;
+        }
+    }
     sh->absorb = ctx->absorb;
     sh->L = L;
     sh->R = R;
@@ -223,7 +234,7 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     sh->teams = teams;
     sh->grid = (int)((U + teams - 1) / teams);
     sh->lds_fwd = (size_t)teams * 2 * W * mp * sizeof(float);
-    sh->lds_bwd = (size_t)teams * per_team_bwd();
+    sh->lds_bwd = (size_t)teams * per_team_bwd() + sh->lds_cb;
     return FR_OK;
 }
 
@@ -631,6 +642,11 @@ fr_status fr_ctx_create(int device, fr_ctx** out) {
     FR_TRY(hipSetDevice(device));
     fr_ctx* c = new fr_ctx();
     c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess &&
+        lds > 0)
+        c->max_lds = (size_t)lds;
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return FR_E_DEVICE;
@@ -1107,6 +1123,18 @@ fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int
     if (st) return st;
     if (fwd_form) *fwd_form = (sh.fwd == sh.fe->fwds) ? FR_FORM_SCALING : FR_FORM_LOG;
     if (bwd_form) *bwd_form = (sh.bwd == sh.fe->bwds) ? FR_FORM_SCALING : FR_FORM_LOG;
+    return FR_OK;
+}
+
+fr_status fr_ctx_bwd_lds_rows(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
+                              int32_t checkpoint_every, int32_t* rows) {
+    if (!ctx || !rows) return FR_E_NULL;
+    if (n_users < 1 || n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems)
+        return FR_E_SHAPE;
+    Shape sh;
+    fr_status st = make_shape(ctx, n_users, n_items, m, resolve_k(checkpoint_every), &sh);
+    if (st) return st;
+    *rows = (sh.bwd == sh.fe->bwdl) ? sh.fe->cb_rows : 0;
     return FR_OK;
 }
 

@@ -854,13 +854,38 @@ __device__ __forceinline__ void fwds_body(const FwdArgs& a, int64_t u_first, flo
 }
 
 // ---------------------------------------------------------------------------
+// Cost adjoints of a lane's R rows: rows j < R - NL in registers, the last NL
+// in LDS, column-major over the team's lanes ((j' MP + k) L + lane), so that
+// the 64 lanes of a wave touch consecutive words.  Every lane owns its slots:
+// no synchronisation is needed.  NL > 0 is for the wide recompute kernels,
+// whose registers cannot hold costs, cost adjoints and a pass's temporaries.
+template <int MP, int R, int NL>
+struct CostAdj {
+    static constexpr int RR = R - NL;
+    float reg[RR > 0 ? RR : 1][MP];
+    float* lds = nullptr;
+    int L = 0, lt = 0;
+    __device__ __forceinline__ float& operator()(int j, int k) {
+        if (j < RR) return reg[j][k];
+        return lds[((j - RR) * MP + k) * L + lt];
+    }
+};
+
+// The same access to a plain register array of cost adjoints.
+template <int MP, int R>
+struct ArrAdj {
+    float (&a)[R][MP];
+    __device__ __forceinline__ float& operator()(int j, int k) { return a[j][k]; }
+};
+
+// ---------------------------------------------------------------------------
 // Backward pieces.  Reverse of iteration t for the lane's rows: gp = gamma^{t-1},
 // gh_k = gbar_k / sig^t_k; cb += P (gh + fbar); the lane's share of
 // sum_i P_ik fbar_i goes to acc (or, recompute variant, to the scattered q).
-template <int MP, int R>
+template <int MP, int R, class CB>
 __device__ __forceinline__ void rev_pass(float (&c)[R][MP], const float (&om)[R],
                                          const float (&gp)[MP], const float (&gh)[MP],
-                                         const float (&fb0)[R], bool first, float (&cb)[R][MP],
+                                         const float (&fb0)[R], bool first, CB& cb,
                                          float (&acc)[MP], float (&off)[R]) {
 #pragma unroll
     for (int k = 0; k < MP; ++k) acc[k] = 0.f;
@@ -877,32 +902,113 @@ __device__ __forceinline__ void rev_pass(float (&c)[R][MP], const float (&om)[R]
         const float aa = w * fb;
 #pragma unroll
         for (int k = 0; k < MP; ++k) {
-            cb[j][k] = fmaf(e[k], fmaf(w, gh[k], aa), cb[j][k]);
+            cb(j, k) = fmaf(e[k], fmaf(w, gh[k], aa), cb(j, k));
             acc[k] = fmaf(e[k], aa, acc[k]);
         }
     }
 }
 
-template <int MP, int R>
-__device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const float (&om)[R],
-                                                const float (&gp)[MP], const float (&gh)[MP],
-                                                const float (&fb0)[R], bool first,
-                                                float (&cb)[R][MP], float (&q)[n_slots(MP)],
-                                                float (&sh)[R]) {
+// Owner broadcast of the columns [K0, K0 + N): out[kk] = x of the lane that
+// owns column K0 + kk, as scalars.
+template <int MP, int K0, int N, int KK = 0>
+__device__ __forceinline__ void spread_range(float x, float (&out)[N]) {
+    if constexpr (KK < N) {
+        out[KK] = lane_value<lane_of(MP, K0 + KK)>(x);
+        spread_range<MP, K0, N, KK + 1>(x, out);
+    }
+}
+
+// Reverse of iteration t for the wide recompute variant (registers too few
+// for a row of exponentials, so every pass recomputes them under a per-row
+// shift sh, as row_stats_shift does).  It never holds a whole row of
+// column values: gamma^{t-1} and gh arrive as the owner lanes' values gpd and
+// ghd and are broadcast chunk by chunk, once per pass (each broadcast from a
+// fresh opaque copy, so that passes do not share them), which leaves only the
+// costs and cost adjoints live across the iteration.
+template <int MP, int R, class CB>
+__device__ __forceinline__ void rev_pass_owned(const float (&c)[R][MP], const float (&om)[R],
+                                               float gpd, float ghd, const float (&fb0)[R],
+                                               bool first, CB& cb,
+                                               float (&q)[n_slots(MP)], float (&sh)[R]) {
+    float s[R], d[R];
+    auto sums = [&](float one) {
+        float ps[R][4], pd[R][4];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) ps[j][p] = pd[j][p] = 0.f;
+        const float gpo = opaque(gpd), gho = opaque(ghd);
+        for_chunks<MP>([&](auto ch) {
+            constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+            float g[ci.n], h[ci.n];
+            spread_range<MP, ci.k0, ci.n>(gpo, g);
+            spread_range<MP, ci.k0, ci.n>(gho, h);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+#pragma unroll
+                for (int kk = 0; kk < ci.n; ++kk) {
+                    const int k = ci.k0 + kk;
+                    const float e = ex2(fmaf(c[j][k], one, g[kk]) - sh[j]);
+                    ps[j][k & 3] += e;
+                    pd[j][k & 3] = fmaf(e, h[kk], pd[j][k & 3]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            s[j] = (ps[j][0] + ps[j][1]) + (ps[j][2] + ps[j][3]);
+            d[j] = (pd[j][0] + pd[j][1]) + (pd[j][2] + pd[j][3]);
+        }
+    };
+    sums(1.f);
+    bool bad[R], anybad = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        bad[j] = !in_range(s[j]);
+        anybad |= bad[j];
+    }
+    if (wave_any(anybad)) {
+        // rare: rows whose sum left range shift to their current maximum
+        const float one = opaque(1.f);
+        float mx[R][4];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) mx[j][p] = kNeg;
+        const float gpo = opaque(gpd);
+        for_chunks<MP>([&](auto ch) {
+            constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
+            float g[ci.n];
+            spread_range<MP, ci.k0, ci.n>(gpo, g);
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int kk = 0; kk < ci.n; ++kk) {
+                    const int k = ci.k0 + kk;
+                    mx[j][k & 3] = fmaxf(mx[j][k & 3], fmaf(c[j][k], one, g[kk]));
+                }
+        });
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (bad[j]) sh[j] = fmaxf(fmaxf(mx[j][0], mx[j][1]), fmaxf(mx[j][2], mx[j][3]));
+        sums(opaque(1.f));
+    }
     float w[R], aa[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        float s, d;
-        row_stats_shift<MP, true>(c[j], gp, gh, s, d, sh[j]);
-        w[j] = om[j] * rcp(s);
-        const float fb = (first ? fb0[j] : 0.f) - w[j] * d;
+        w[j] = om[j] * rcp(s[j]);
+        const float fb = (first ? fb0[j] : 0.f) - w[j] * d[j];
         aa[j] = w[j] * fb;
     }
     __builtin_amdgcn_sched_barrier(0);
     const float one = opaque(1.f);
+    const float gpo = opaque(gpd), gho = opaque(ghd);
     for_chunks<MP>([&](auto ch) {
         constexpr ChunkInfo ci = chunk_info(MP, decltype(ch)::value);
-        float v[ci.n];
+        float g[ci.n], h[ci.n], v[ci.n];
+        spread_range<MP, ci.k0, ci.n>(gpo, g);
+        spread_range<MP, ci.k0, ci.n>(gho, h);
 #pragma unroll
         for (int kk = 0; kk < ci.n; ++kk) v[kk] = 0.f;
 #pragma unroll
@@ -910,14 +1016,14 @@ __device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const f
 #pragma unroll
             for (int kk = 0; kk < ci.n; ++kk) {
                 const int k = ci.k0 + kk;
-                const float e = ex2(fmaf(c[j][k], one, gp[k]) - sh[j]);
-                cb[j][k] = fmaf(e, fmaf(w[j], gh[k], aa[j]), cb[j][k]);
+                const float e = ex2(fmaf(c[j][k], one, g[kk]) - sh[j]);
+                cb(j, k) = fmaf(e, fmaf(w[j], h[kk], aa[j]), cb(j, k));
                 v[kk] = fmaf(e, aa[j], v[kk]);
             }
         }
         scatter_chunk<MP, decltype(ch)::value>(v, q);
+        __builtin_amdgcn_sched_barrier(0);
     });
-    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Start of the reverse sweep (t = T): X = P^T diag(rho), rho_k = b_k / sig^T_k,
@@ -925,11 +1031,11 @@ __device__ __forceinline__ void rev_pass_recomp(const float (&c)[R][MP], const f
 // fb0 = (G X) 1 / eps, acc (or q) = the lane's share of (G X)^T 1 / eps;
 // also dr = gF e.X / Imp.  Rows are processed chunk by chunk with the
 // exponentials recomputed, so no row of them is kept.
-template <int MP, int R, bool WIDE>
+template <int MP, int R, bool WIDE, class CB>
 __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][MP],
                                          const float (&om)[R], const float (&gp)[MP],
                                          const float (&rho)[MP], const float (&rg)[R],
-                                         float (&fb0)[R], float (&cb)[R][MP],
+                                         float (&fb0)[R], CB& cb,
                                          float (&acc)[WIDE ? 1 : MP], float (&q)[n_slots(MP)],
                                          float (&sh)[R], int64_t u, bool active, const Team& tm) {
     const int m = opaque_u(a.m);
@@ -959,7 +1065,7 @@ __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][M
                 // xs = x / eps, gx = G x / eps
                 const float xs = ex2(fmaf(c[j][k], one, gp[k]) - sh[j]) * w[j] * rho[k];
                 const float gx = rg[j] * ek[k] * xs;
-                cb[j][k] = -gx;
+                cb(j, k) = -gx;
                 fb0[j] += gx;
                 v[kk] += gx;
                 xe[j] = fmaf(ek[k], xs, xe[j]);
@@ -983,9 +1089,8 @@ __device__ __forceinline__ void rev_init(const BwdArgs& a, const float (&c)[R][M
 // Backward epilogue for the lane's rows: writes gF * dF/dC, or applies Adam /
 // ascent to C in place (re-reading C from HBM: the registers hold transformed
 // costs).
-template <int MP, int R>
-__device__ __forceinline__ void bwd_epilogue(const BwdArgs& a, const float (&cb)[R][MP], int64_t u,
-                                             const Team& tm) {
+template <int MP, int R, class CB>
+__device__ __forceinline__ void bwd_epilogue(const BwdArgs& a, CB& cb, int64_t u, const Team& tm) {
     const int I = a.I, m = a.m;
     const int mo = opaque_u(m);
     float bc1 = 1.f, bc2 = 1.f;
@@ -1002,7 +1107,7 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs& a, const float (&cb)
 #pragma unroll
         for (int k = 0; k < MP; ++k) {
             if (k >= mo) continue;
-            const float g = cb[j][k];
+            const float g = cb(j, k);
             if (a.dC) a.dC[base + k] = g;
             if (a.Cw) {
                 const float craw = a.C[base + k];   // the registers do not hold raw costs
@@ -1021,7 +1126,9 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs& a, const float (&cb)
     }
 }
 
-template <int MP, int R, bool WIDE, bool RECOMP>
+// NL: rows of cost adjoints per lane kept in LDS (after the block's segment
+// and reduction buffers, NL * MP * L floats per team).
+template <int MP, int R, bool WIDE, bool RECOMP, int NL = 0>
 __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, float* smem) {
     const Team tm = make_team(a.L);
     const int teams = blockDim.x / a.L;
@@ -1046,7 +1153,13 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
     cs.init(tm, m, lg2((float)(I - m + 1)), 1.0f / (float)(I - m + 1), gam);
 
     const float* hist = active ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
-    float cb[R][MP], fb0[R], Sf[R], sh[R], shf[R];
+    CostAdj<MP, R, NL> cb;
+    if constexpr (NL > 0) {
+        cb.lds = smem + teams * ((BL + 1) * MP + 2 * tm.W * MP) + tm.team * (NL * MP * tm.L);
+        cb.L = tm.L;
+        cb.lt = tm.lt;
+    }
+    float fb0[R], Sf[R], sh[R], shf[R];
     float gbar[WIDE ? 1 : MP];   // narrow: every column; wide: the owned column
 #pragma unroll
     for (int k = 0; k < (WIDE ? 1 : MP); ++k) gbar[k] = 0.f;
@@ -1093,6 +1206,27 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
             const int t = t0 + qq;
             const float* sq = seg + qq * MP;        // gamma^t
             const float* sp = seg + (qq - 1) * MP;  // gamma^{t-1}
+            if constexpr (WIDE && RECOMP) {
+                // column values stay with their owner lanes (rev_pass_owned)
+                const float gpd = (cs.col >= 0) ? sp[cs.col] : kNeg;
+                if (t == a.T) {
+                    float gp[MP], rho[MP];
+                    spread_owned<MP>(gpd, gp);
+#pragma unroll
+                    for (int k = 0; k < MP; ++k) rho[k] = ex2(sq[k] - gp[k]);   // 1 on padding
+                    float acc[1];
+                    float q[n_slots(MP)];
+                    rev_init<MP, R, WIDE>(a, c, om, gp, rho, rg, fb0, cb, acc, q, sh, u, active, tm);
+                    gbar[0] = wide_total<MP>(q, tm, cs.col, red, par);
+                    par ^= 1;
+                }
+                const float ghd = cs.live ? gbar[0] * ex2(sq[cs.col] - sp[cs.col]) * cs.ibc : 0.f;
+                float q[n_slots(MP)];
+                rev_pass_owned<MP, R>(c, om, gpd, ghd, fb0, t == a.T, cb, q, sh);
+                gbar[0] = -wide_total<MP>(q, tm, cs.col, red, par);
+                par ^= 1;
+                continue;
+            }
             float gp[MP], gh[MP];
             if constexpr (WIDE) {
                 spread_owned<MP>((cs.col >= 0) ? sp[cs.col] : kNeg, gp);
@@ -1130,13 +1264,9 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& a, int64_t u_first, floa
             // reverse of iteration t
             if constexpr (WIDE) {
                 float q[n_slots(MP)];
-                if constexpr (RECOMP) {
-                    rev_pass_recomp<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, q, sh);
-                } else {
-                    float acc[MP];
-                    rev_pass<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, acc, off);
-                    scatter_all<MP>(acc, q);
-                }
+                float acc[MP];
+                rev_pass<MP, R>(c, om, gp, gh, fb0, t == a.T, cb, acc, off);
+                scatter_all<MP>(acc, q);
                 gbar[0] = -wide_total<MP>(q, tm, cs.col, red, par);
             } else {
                 float acc[MP];
@@ -1746,7 +1876,10 @@ __device__ __forceinline__ void bwds_body(const BwdArgs& a, int64_t u_first, flo
             par ^= 1;
         }
     }
-    if (active) bwd_epilogue<MP, R>(a, cb, u, tm);
+    if (active) {
+        ArrAdj<MP, R> cba{cb};
+        bwd_epilogue<MP, R>(a, cba, u, tm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1800,6 +1933,28 @@ __global__ __launch_bounds__(LB) void k_bwd(BwdArgs a) {
     if (a.stop && *a.stop) return;   // the outer loop has ended
     bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, (int64_t)blockIdx.x * (blockDim.x / a.L),
                                                      smem);
+}
+
+// Rows of cost adjoints per lane that the wide recompute reverse sweep keeps
+// in LDS at launch bound LB (512 or 1024: one team per block): as many as fit,
+// with the segment and reduction buffers of K = 1, in 144 KB of the 160 KB of
+// LDS, all but one row at most.
+template <int R, int LB, bool WIDE>
+constexpr int cb_lds_rows() {
+    if (!(WIDE && LB >= 512 && recomp_bwd<R, LB, WIDE>())) return 0;
+    for (int n = R - 1; n >= 1; --n)
+        if ((n * LB + (kLoadBlock + 1) + 2 * (LB / 64)) * FR_MP * 4 <= 144 * 1024) return n;
+    return 0;
+}
+
+// k_bwd with cb_lds_rows() rows of cost adjoints in LDS.
+template <int MP, int R, int LB, bool WIDE>
+__global__ __launch_bounds__(LB) void k_bwdl(BwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    if constexpr (cb_lds_rows<R, LB, WIDE>() > 0)
+        bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>(), cb_lds_rows<R, LB, WIDE>()>(
+            a, (int64_t)blockIdx.x * (blockDim.x / a.L), smem);
 }
 
 template <int MP, int R, int LB, bool WIDE>
@@ -1893,6 +2048,10 @@ void launch_bwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s
     hipLaunchKernelGGL((k_bwd<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
 template <int MP, int R, int LB, bool WIDE>
+void launch_bwdl(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_bwdl<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
+}
+template <int MP, int R, int LB, bool WIDE>
 void launch_bwds(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_bwds<MP, R, LB, WIDE>), dim3(grid), dim3(block), lds, s, a);
 }
@@ -1931,13 +2090,18 @@ constexpr FusedEntry entry() {
                           &occupancy_bfwd<FR_MP, R, WIDE, true>,
                           &launch_bwds<FR_MP, R, LB, WIDE>,
                           &launch_bbwd<FR_MP, R, WIDE, true>,
-                          &occupancy_bbwd<FR_MP, R, WIDE, true>};
+                          &occupancy_bbwd<FR_MP, R, WIDE, true>,
+                          nullptr,
+                          0};
     } else {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,
                           &launch_fwdc<FR_MP, R, LB, WIDE>, &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_fwds<FR_MP, R, LB, WIDE>, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, nullptr, &launch_bwds<FR_MP, R, LB, WIDE>, nullptr, nullptr};
+                          nullptr, nullptr, &launch_bwds<FR_MP, R, LB, WIDE>, nullptr, nullptr,
+                          cb_lds_rows<R, LB, WIDE>() > 0 ? &launch_bwdl<FR_MP, R, LB, WIDE>
+                                                         : nullptr,
+                          cb_lds_rows<R, LB, WIDE>()};
     }
 }
 

@@ -103,6 +103,8 @@ struct FusedEntry {
     BwdLaunch bwds;     // scaling-form reverse sweep (K = 1)
     BBwdLaunch bbwds;   // batched scaling-form reverse sweep (K = 1)
     Occupancy occ_bbwds;
+    BwdLaunch bwdl;     // reverse sweep with cb_rows rows of cost adjoints in LDS (or null)
+    int cb_rows;
 };
 
 // Instantiated column classes.  Each class is compiled in its own translation

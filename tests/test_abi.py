@@ -173,4 +173,8 @@ def test_newer_entry_points_reject_null_context(lib):
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p]
     assert lib.fr_ctx_kernel_forms(None, 10, 20, 5, 0, None, None) == 1
+    lib.fr_ctx_bwd_lds_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    rows = ctypes.c_int32()
+    assert lib.fr_ctx_bwd_lds_rows(None, 10, 20, 5, 0, ctypes.byref(rows)) == 1
     assert lib.fr_solve_progress(None, 1, None, None, None, None) == 1
