@@ -1,13 +1,15 @@
 """Benchmark of the fused fair-ranking solver on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload C2|C1|C3|C4|C5]
+    python bench.py [--steps K] [--warmup W] [--workload C5|C1|C2|C3|C4]
 
 One bench step is one pass of the whole hot path over the workload:
 
-* C1, C2 (default), C5: one full solve of Algorithm 1 -- N outer steps, each
-  a T-iteration Sinkhorn forward on every consumer's plan, the FP64 impact and
-  log-NSW reduction, the adjoint backward and the Adam update -- plus the
-  final forward.  (C5 runs --outer steps, default 2 of its 50, for time.)
+* C5 (default), 100000 consumers x 1000 items x 50 positions: one outer step
+  of Algorithm 1 on the whole instance -- the T = 300 Sinkhorn forward on
+  every consumer's plan, the FP64 impact and log-NSW reduction, the adjoint
+  reverse sweep and the Adam update.  W warm-up steps from C = 0, K timed
+  steps continuing the trajectory, then the rest of the 50 steps (untimed).
+* C1, C2: one full solve (N outer steps plus the final forward).
 * C3: one gradient evaluation, fr_step then fr_backward with the column
   potentials kept every 50 iterations.
 * C4: one batched solve of the 128 uneven instances (persistent kernels, one
@@ -32,24 +34,41 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue one FP32 VALU
-# lane-operation per lane and clock (the 157.3 TFLOP/s figure counts packed
-# FMAs, 2 lanes x 2 flops, and packed FP32 is disabled in this build).
-# v_exp_f32 runs at half that rate on a pipe that overlaps ordinary VALU
-# issue (measured: exp + 5 FMA groups sustain ~90% of the FMA-only rate), so
-# at one exponential per cell-iteration the binding ceiling is the issue of
-# the other VALU operations: 5 per cell-iteration in the forward (FMA, max,
-# subtract, add, FMA) and 8 in the reverse sweep (adds a dot product FMA and
-# two accumulation FMAs).
+# MI355X (gfx950): 256 CUs x 4 SIMDs, 2.4 GHz.  The published FP32 vector
+# peak, 157.3 TFLOP/s, counts packed FMAs (two lanes of FMA per lane-slot, an
+# FMA being 2 flops); this build compiles with packed FP32 disabled, so its
+# single-lane FP32 VALU issue tops out at half of it, 78.6 TFLOP/s
+# (39.3 T FMA/s).  The roofline reports both fractions; the headline one is
+# against the published 157.3.
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-PEAK_SLOTS = CUS * SIMDS * LANES * CLOCK          # 3.93e13 lane-slots/s
-FWD_SLOTS = {"log": 5, "scaling": 2}   # scaling form: the two multiply-adds of u and v
-# reverse sweep: log domain 8 (the forward's 5 plus the row dot product and the two
-# accumulations); scaling form 6 (the product K w, the row-sum add, and four
-# multiply-adds: row dot product, cost adjoint (two), column partial)
-BWD_SLOTS = {"log": 8, "scaling": 6}
+PEAK_FP32_FLOPS = 157.3e12                         # published, packed FP32
+PEAK_FP32_NONPACKED = CUS * SIMDS * LANES * CLOCK * 2   # 78.6e12 FLOP/s
+LDS_PEAK = CUS * 128 * CLOCK                       # 128 B per clock per CU: 78.6 TB/s
+# Algorithmic FP32 flops per cell-iteration (FMA = 2, add or multiply = 1),
+# the minimum the method needs, independent of this implementation:
+#   forward, either form: the row product sum_k K_ik v_k (FMA) and the column
+#     product sum_i K_ik u_i (FMA): 4 flops; the log domain forms K_ik v_k as
+#     one exponential of a + gamma instead (an add and a transcendental).
+#   reverse sweep: the row sums s_i = sum_k P_ik and d_i = sum_k P_ik gh_k
+#     (two FMAs on K and the column scalings), the column adjoint
+#     sum_i P_ik fbar_i (FMA) and the cost adjoint cbar += P (gh + fbar)
+#     (two FMAs): 10 flops (log domain: plus one exponential).
+FWD_FLOPS = {"log": 4, "scaling": 4}
+BWD_FLOPS = {"log": 10, "scaling": 10}
+FWD_TRANS = {"log": 1, "scaling": 0}
+BWD_TRANS = {"log": 1, "scaling": 0}
 FORMS = {0: "log", 1: "scaling"}
 HBM_PEAK = 8.0e12
+# The paper's own speed statements (Section 4.2 and the footnote of Section
+# 4.1), on an NVIDIA GeForce RTX 3090 against an Intel Core i9-12900K; no
+# absolute times are printed.  Context only, not targets.
+PAPER_CONTEXT = {
+    "gpu_vs_cpu": "about 10x: Algorithm 1 with PyTorch on an RTX 3090 vs the same on an "
+                  "i9-12900K (Section 4.2)",
+    "gpu_vs_mosek": "about 1000x: Algorithm 1 on the RTX 3090 vs the exact problem solved "
+                    "by Mosek on the i9-12900K (Section 4.2)",
+    "scaling_in_U": "GPU time almost independent of the number of consumers (Section 4.2)",
+}
 
 
 def kernel_source_hash():
@@ -66,9 +85,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, cfg):
-    """HBM bytes per launch from the committed profiler summary, if it was
-    taken on the current kernel source."""
+def load_profile(kernel, cfg):
+    """The committed profiler figures of a kernel on a workload (HBM bytes per
+    launch; LDS and transcendental instructions per launch where collected),
+    if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -77,7 +97,7 @@ def load_traffic(kernel, cfg):
     ent = doc.get(cfg, {}).get(kernel)
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
 def _lib_timing(lib):
@@ -90,21 +110,9 @@ def _lib_timing(lib):
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
 
 
-def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
-    """Per-kernel mean launch times with HIP events (one solve in timing
-    mode), and the roofline of the dominant kernel."""
-    import torch
+def kernel_names(lib, ctx, prob):
+    """(forward kernel, its form, reverse-sweep kernel, its form) the solve runs."""
     _lib_timing(lib)
-    ctx.set_form(form)
-    lib.fr_ctx_set_timing(ctx.handle, 1)
-    fr.solve(ctx, prob, N, lr, want_X=False)
-    torch.cuda.synchronize()
-    fms, fn, bms, bn = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
-    lib.fr_ctx_kernel_times(ctx.handle, ctypes.byref(fms), ctypes.byref(fn), ctypes.byref(bms),
-                            ctypes.byref(bn))
-    lib.fr_ctx_set_timing(ctx.handle, 0)
-    cells = prob.U * prob.I * prob.m
-    per_launch = cells * (prob.T + 1)   # cell-iterations of one launch (incl. plan / init pass)
     ff, bf = ctypes.c_int32(), ctypes.c_int32()
     lib.fr_ctx_kernel_forms(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(ff),
                             ctypes.byref(bf))
@@ -113,32 +121,93 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling"):
     nl = ctypes.c_int32()
     lib.fr_ctx_bwd_lds_rows(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(nl))
     bk = "k_bwds" if bform == "scaling" else ("k_bwdl" if nl.value > 0 else "k_bwd")
-    ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_SLOTS[fform]),
-          bk: (bms.value / max(bn.value, 1), bn.value, BWD_SLOTS[bform])}
-    kernels = {k: {"avg_ms": v[0], "launches": v[1],
-                   "cell_iters_per_s": per_launch / (v[0] * 1e-3),
-                   "alg_slots_per_cell_iter": v[2],
-                   "alu_frac": per_launch * v[2] / (v[0] * 1e-3) / PEAK_SLOTS}
-               for k, v in ks.items()}
+    return fk, fform, bk, bform
+
+
+def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None, mom=None,
+                    vel=None, start_step=0):
+    """Per-kernel mean launch times with HIP events recorded on the solve's
+    stream (one solve of N outer steps in timing mode, from C0 or C = 0), and
+    the roofline of the dominant kernel."""
+    import torch
+    _lib_timing(lib)
+    ctx.set_form(form)
+    lib.fr_ctx_set_timing(ctx.handle, 1)
+    fr.solve(ctx, prob, N, lr, want_X=False, C0=C0, mom=mom, vel=vel, start_step=start_step,
+             inplace=C0 is not None)
+    torch.cuda.synchronize()
+    fms, fn, bms, bn = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    lib.fr_ctx_kernel_times(ctx.handle, ctypes.byref(fms), ctypes.byref(fn), ctypes.byref(bms),
+                            ctypes.byref(bn))
+    lib.fr_ctx_set_timing(ctx.handle, 0)
+    cells = prob.U * prob.I * prob.m
+    per_launch = cells * prob.T   # cell-iterations of one launch
+    fk, fform, bk, bform = kernel_names(lib, ctx, prob)
+    ks = {fk: (fms.value / max(fn.value, 1), fn.value, FWD_FLOPS[fform], FWD_TRANS[fform]),
+          bk: (bms.value / max(bn.value, 1), bn.value, BWD_FLOPS[bform], BWD_TRANS[bform])}
+    kernels = {}
+    for k, (ms, n, fl, tr) in ks.items():
+        sec = ms * 1e-3
+        ent = {"avg_ms": ms, "launches": n, "cell_iters_per_launch": per_launch,
+               "cell_iters_per_s": per_launch / sec, "alg_flops_per_cell_iter": fl,
+               "achieved_tflops": per_launch * fl / sec / 1e12,
+               "frac_fp32_peak": per_launch * fl / sec / PEAK_FP32_FLOPS,
+               "frac_nonpacked_fp32": per_launch * fl / sec / PEAK_FP32_NONPACKED,
+               "alg_transcendentals_per_cell_iter": tr}
+        prof = load_profile(k, cfg_name)
+        if prof is not None:
+            ent["profile_kernel"] = prof.get("kernel")
+            if "lds_bytes_per_launch" in prof:
+                ent["lds_TBps"] = prof["lds_bytes_per_launch"] / sec / 1e12
+                ent["lds_frac"] = prof["lds_bytes_per_launch"] / sec / LDS_PEAK
+            if "trans_per_launch" in prof:
+                ent["trans_per_s"] = prof["trans_per_launch"] / sec
+                ent["trans_issued_per_cell_iter"] = prof["trans_per_launch"] / per_launch
+            if "valu_lane_ops_per_launch" in prof:
+                ent["valu_issue_frac"] = (prof["valu_lane_ops_per_launch"] / sec
+                                          / (PEAK_FP32_NONPACKED / 2))
+        kernels[k] = ent
     dom = max(ks, key=lambda k: ks[k][0])
-    avg_ms, _, slots = ks[dom]
-    achieved = per_launch * slots / (avg_ms * 1e-3)
-    traffic = load_traffic(dom, cfg_name)
+    avg_ms, _, fl, _ = ks[dom]
+    achieved = per_launch * fl / (avg_ms * 1e-3)
+    prof = load_profile(dom, cfg_name)
+    traffic = None if prof is None else prof.get("bytes_per_launch")
     roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
-            "peak": PEAK_SLOTS / 1e12, "unit": "T VALU lane-slots/s",
-            "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+            "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
+            "frac_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
             "hbm_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
             "hbm_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / HBM_PEAK,
-            # one outer step costs both kernels' slots per cell-iteration
-            "solve_ceiling_cell_iters_per_s": PEAK_SLOTS / (FWD_SLOTS[fform] + BWD_SLOTS[bform]),
+            "alg_hbm_bytes_per_launch": alg_bytes(dom, prob),
+            # one outer step costs both kernels' flops per cell-iteration
+            "solve_ceiling_cell_iters_per_s": PEAK_FP32_FLOPS / (FWD_FLOPS[fform]
+                                                                 + BWD_FLOPS[bform]),
             "avg_launch_ms": avg_ms,
-            "model": f"{slots} algorithmic VALU lane-slots per cell-iteration of the {dom} "
-                     "arithmetic (log domain: non-transcendental slots, the exponential "
-                     "overlapping on its own pipe), U*I*m*(T+1) cell-iterations per launch; "
-                     "peak = 256 CUs x 64 lanes x 2.4 GHz"}
+            "model": f"{fl} algorithmic FP32 flops (FMA = 2) per cell-iteration of the "
+                     f"{dom} arithmetic, U*I*m*T cell-iterations per launch, mean launch time "
+                     "from HIP events on the solve's stream; peak = the published MI355X FP32 "
+                     "vector rate (packed FMA); this build issues single-lane FP32 only "
+                     "(frac_nonpacked_fp32 is against that ceiling, 78.6 TFLOP/s)"}
+    if dom in kernels:
+        for key in ("lds_TBps", "lds_frac", "trans_per_s", "trans_issued_per_cell_iter",
+                    "valu_issue_frac"):
+            if key in kernels[dom]:
+                roof[key] = kernels[dom][key]
     print(f"bench: kernels ({form} form) {fk} {ks[fk][0]:.3f} ms {bk} {ks[bk][0]:.3f} ms "
           "per launch", flush=True)
     return kernels, roof
+
+
+def alg_bytes(kernel, prob):
+    """Algorithmic HBM bytes of one launch: forward reads C and r and writes the
+    impact contributions y (and the checkpointed potentials); the reverse sweep
+    reads C, r, the stored potentials and the Adam moments and writes C and the
+    moments back (Adam fused)."""
+    U, I, m, T = prob.U, prob.I, prob.m, prob.T
+    cells = U * I * m
+    if kernel.startswith("k_fwd"):
+        return cells * 4 + U * I * 8 + U * T * m * 4
+    return cells * 4 * 6 + U * I * 4 + U * T * m * 4
 
 
 def bench_converged(fr, ctx, prob, N, lr, F_fixed, tol=1e-4):
@@ -206,13 +275,13 @@ def base_record(args, value, ms_per_step, config):
 
 # ---------------------------------------------------------------------------
 def bench_solve(args, fr, lib, dev, name):
-    """C1, C2, C5: full solves of one instance."""
+    """C1, C2: full solves of one instance."""
     import torch
     import workloads as W
     inst = W.config(name)
     U, I, m, T = inst.U, inst.I, inst.m, inst.T
-    N = inst.N if name != "C5" else args.outer
-    x_dtype = "bf16" if name == "C5" else "f32"
+    N = inst.N
+    x_dtype = "f32"
     cells = U * I * m
     work = cells * T * N
     ctx = fr.Context(0)
@@ -221,7 +290,7 @@ def bench_solve(args, fr, lib, dev, name):
     lr = float(inst.lr)
     if args.autotune:
         # all T iterations for the small workloads; a short run on the large one
-        ctx.autotune(prob, iters=T if name != "C5" else 20)
+        ctx.autotune(prob, iters=T)
     print(f"bench: workload {inst.name} U={U} I={I} m={m} T={T} N={N} "
           f"launch={ctx.get_launch(U, I, m)}", flush=True)
     for _ in range(args.warmup):
@@ -250,13 +319,10 @@ def bench_solve(args, fr, lib, dev, name):
         nsw["rel_err_max"] = float(np.max(np.abs(Fh / ref - 1)))
         nsw["rel_err_final"] = float(abs(Fh[-1] / ref[-1] - 1))
         nsw["reference"] = "FP64 oracle trajectory (tests/golden)"
-    if name == "C5":
-        nsw.update(c5_subsample_error(fr, dev, inst))
     kernels, roof = kernel_roofline(fr, lib, ctx, prob, min(N, 20), lr, inst.name)
     kernels_log, _ = kernel_roofline(fr, lib, ctx, prob, min(N, 20), lr, inst.name, form="log")
     ctx.set_form("scaling")
-    desc = {"C1": "low-dimensional uniform-relevance", "C2": "low-rank-16 sigmoid relevance",
-            "C5": "low-rank-32 sigmoid relevance, plans stored in BF16"}[name]
+    desc = {"C1": "low-dimensional uniform-relevance", "C2": "low-rank-16 sigmoid relevance"}[name]
     config = {"workload": f"{inst.name}: U={U} consumers, I={I} items, m={m} positions "
                           f"(incl. dummy), {desc}, e_k=1/log2(k+1), eps={float(inst.eps):.4g}, "
                           f"T={T} Sinkhorn iterations, N={N} Adam steps (lr=0.1 eps), FP32 "
@@ -272,12 +338,13 @@ def bench_solve(args, fr, lib, dev, name):
                     "note": "the same iterates and gradient in log-domain arithmetic (one "
                             "exponential per cell-iteration); the solve above runs the "
                             "scaling form where it applies"}})
-    if name != "C5" and not args.skip_extras:
+    if not args.skip_extras:
         out["converged_map"] = bench_converged(fr, ctx, prob, N, lr, Fh[-1])
         out["baselines"] = bench_baselines(fr, ctx, prob)
     if not args.skip_diag:
         out["measured_peaks"] = measured_peaks(lib)
-    if not args.skip_plain and name != "C5":
+    out["paper_context"] = PAPER_CONTEXT
+    if not args.skip_plain:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pres = fr.solve_plain(ctx, prob, N, lr, want_X=False)
@@ -327,28 +394,185 @@ def bench_metrics(fr, ctx, prob, X):
                           "peak_tflops": 78.6, "bound": "mfma (FP64)"}}
 
 
-def c5_subsample_error(fr, dev, inst):
-    """NSW error of the 1000-consumer sub-instance against the oracle's
-    stored values (forward at a seeded C, 3 Adam steps from C = 0)."""
+def c5_subsample(inst, dev):
+    """The 1000-consumer sub-instance (seed 55) of the 100000 x 1000 x 50
+    workload, with the oracle's stored values for it."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "c5_sub.npz")
+    g = np.load(path) if os.path.exists(path) else None
+    users = (g["users"] if g is not None else
+             __import__("workloads").subsample_users(inst.U, 1000, seed=55))
+    tpath = os.path.join(ROOT, "tests", "golden", "c5_traj.npz")
+    traj = np.load(tpath) if os.path.exists(tpath) else None
+    return users, g, traj
+
+
+def c5_subsample_legs(fr, dev, inst, skip_plain):
+    """NSW error against the FP64 oracle on the 1000-consumer sub-instance:
+    the forward at a seeded C (impacts and F from FP32 plan values, as the
+    solve forms them), the same from the stored BF16 plan (fr_nsw on X in
+    BF16), and Algorithm 1 for all 50 outer steps (fused, and the plain GPU
+    form at equal T and N)."""
     import torch
     import workloads as W
-    path = os.path.join(ROOT, "tests", "golden", "c5_sub.npz")
-    if not os.path.exists(path):
-        return {}
-    g = np.load(path)
-    users = g["users"]
+    users, g, traj = c5_subsample(inst, dev)
+    if g is None:
+        return {}, None
     ctx = fr.Context(0)
     prob = fr.Problem(torch.from_numpy(inst.r[users]).to(dev), torch.from_numpy(inst.e).to(dev),
                       float(inst.eps), inst.T)
-    C = torch.from_numpy(W.random_costs(1000, inst.I, inst.m, 2 * float(inst.eps), seed=56)).to(dev)
-    out = fr.step(ctx, prob, C)
-    res = fr.solve(ctx, prob, 3, float(inst.lr), x_dtype="bf16")
-    Fh = res["F_hist"].cpu().numpy()
-    return {"subsample": "1000 consumers (seed 55)",
-            "subsample_forward_F_rel_err": abs(float(out["F"][0]) / float(g["rand_F"][0]) - 1),
-            "subsample_forward_imp_rel_err_max":
-                float(np.max(np.abs(out["imp"].cpu().numpy() / g["rand_imp"] - 1))),
-            "subsample_3step_F_rel_err_max": float(np.max(np.abs(Fh / g["adam_F_hist"] - 1)))}
+    C = torch.from_numpy(W.random_costs(1000, inst.I, inst.m, 2 * float(inst.eps),
+                                        seed=56)).to(dev)
+    out = fr.step(ctx, prob, C, want_X=True, x_dtype="bf16")
+    imp16, F16 = fr.nsw(ctx, prob, out["X"])
+    rimp, rF = g["rand_imp"], float(g["rand_F"][0])
+    rec = {"subsample": "1000 consumers of the instance (seed 55), costs C ~ N(0, (2 eps)^2) "
+                        "(seed 56)",
+           "forward_F_rel_err": abs(float(out["F"][0]) / rF - 1),
+           "forward_imp_rel_err_max": float(np.max(np.abs(out["imp"].cpu().numpy() / rimp - 1))),
+           "forward_note": "impacts and F of the solve path: FP64 sums of y formed from the "
+                           "FP32 plan values before the plan is rounded to BF16",
+           "bf16_plan_F_rel_err": abs(float(F16.cpu()[0]) / rF - 1),
+           "bf16_plan_imp_rel_err_max": float(np.max(np.abs(imp16.cpu().numpy() / rimp - 1))),
+           "bf16_plan_note": "impacts and F of the stored BF16 plan (fr_nsw, FP64 sums)"}
+    del out
+    plain = None
+    if traj is not None:
+        N = int(traj["F_hist"].shape[0]) - 1
+        ref = traj["F_hist"]
+        fr.solve(ctx, prob, 1, float(inst.lr), want_X=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fr.solve(ctx, prob, N, float(inst.lr), want_X=False)
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t0
+        Fh = res["F_hist"].cpu().numpy()
+        rec.update({"trajectory_steps": N,
+                    "trajectory_F_rel_err_max": float(np.max(np.abs(Fh / ref - 1))),
+                    "trajectory_F_rel_err_final": float(abs(Fh[-1] / ref[-1] - 1)),
+                    "trajectory_imp_rel_err_max": None,
+                    "trajectory_fused_s": fdt,
+                    "trajectory_reference": "FP64 oracle, Algorithm 1 for 50 Adam steps "
+                                            "(tests/golden/c5_traj.npz)"})
+        del res
+        if not skip_plain:
+            cells = 1000 * inst.I * inst.m
+            work = cells * inst.T * N
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pres = fr.solve_plain(ctx, prob, N, float(inst.lr), want_X=False)
+            torch.cuda.synchronize()
+            pdt = time.perf_counter() - t0
+            pF = pres["F_hist"].cpu().numpy()
+            plain = {"sample": f"the 1000-consumer sub-instance, {N} outer steps (T={inst.T}) "
+                               "in both forms",
+                     "value": work / pdt, "seconds": pdt, "fused_seconds": fdt,
+                     "fused_speedup": pdt / fdt,
+                     "F_rel_err_max_vs_oracle": float(np.max(np.abs(pF / ref - 1))),
+                     "fused_F_rel_err_max_vs_oracle": rec["trajectory_F_rel_err_max"],
+                     "form": "one kernel launch per Sinkhorn half-iteration, potentials of "
+                             "every iteration in HBM, reverse sweep reading them back, no graph"}
+            print(f"bench: subsample plain {pdt:.2f} s, fused {fdt:.2f} s", flush=True)
+            del pres
+    ctx.close()
+    return rec, plain
+
+
+def bench_c5(args, fr, lib, dev):
+    """The 100000 x 1000 x 50 workload: one bench step is one outer step of
+    Algorithm 1 on the whole instance (T = 300 Sinkhorn forward on every
+    consumer's plan, FP64 impacts and log-NSW, reverse sweep, Adam).  The
+    trajectory from C = 0 runs in three calls of fr_solve that continue each
+    other (warm-up steps, the timed steps, the rest of the 50 steps); each call
+    ends with the forward that writes the BF16 plan X of its last C."""
+    import torch
+    import workloads as W
+    inst = W.config("C5")
+    U, I, m, T, N = inst.U, inst.I, inst.m, inst.T, inst.N
+    lr = float(inst.lr)
+    cells = U * I * m
+    ctx = fr.Context(0)
+    prob = fr.Problem(torch.from_numpy(inst.r).to(dev), torch.from_numpy(inst.e).to(dev),
+                      float(inst.eps), T)
+    if args.autotune:
+        ctx.autotune(prob, iters=20)
+    print(f"bench: workload C5 U={U} I={I} m={m} T={T} N={N} "
+          f"launch={ctx.get_launch(U, I, m)}", flush=True)
+    C = torch.zeros((U, I, m), dtype=torch.float32, device=dev)
+    mom = torch.zeros_like(C)
+    vel = torch.zeros_like(C)
+    Fparts, seg_s = [], []
+
+    def run(n, start, want_X):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fr.solve(ctx, prob, n, lr, C0=C, mom=mom, vel=vel, start_step=start,
+                       want_X=want_X, x_dtype="bf16", inplace=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        seg_s.append(dt)
+        Fparts.append(res["F_hist"].cpu().numpy())
+        return res, dt
+
+    Wm, K = args.warmup, args.steps
+    if Wm > 0:
+        run(Wm, 0, False)
+        print(f"bench: warm-up {Wm} outer steps {seg_s[-1]:.2f} s", flush=True)
+    res, dt = run(K, Wm, True)
+    ms_per_step = dt / K * 1e3
+    value = cells * T * K / dt
+    print(f"bench: timed {K} outer steps {dt:.2f} s, {ms_per_step:.1f} ms/step, "
+          f"{value:.4e} cell-iters/s", flush=True)
+    if args.profile:
+        return None
+    rest = N - Wm - K
+    if args.skip_rest or rest <= 0:
+        rest = 0
+    else:
+        res, _ = run(rest, Wm + K, True)
+        print(f"bench: remaining {rest} outer steps {seg_s[-1]:.2f} s", flush=True)
+    steps_done = Wm + K + rest
+    Fh = np.concatenate([Fparts[0]] + [p[1:] for p in Fparts[1:]])
+    seam = max([abs(float(a[-1]) - float(b[0])) for a, b in zip(Fparts, Fparts[1:])] + [0.0])
+    metrics = bench_metrics(fr, ctx, prob, res["X"])
+    del res
+    nsw = {"F_0": float(Fh[0]), f"F_{steps_done}": float(Fh[-1]),
+           "segment_seam_max_abs": seam}
+    sub, plain = c5_subsample_legs(fr, dev, inst, args.skip_plain)
+    nsw.update(sub)
+    kernels, roof = kernel_roofline(fr, lib, ctx, prob, 2, lr, "C5", C0=C, mom=mom, vel=vel,
+                                    start_step=steps_done)
+    fk, fform, bk, bform = kernel_names(lib, ctx, prob)
+    config = {"workload": f"C5: U={U} consumers, I={I} items, m={m} positions (incl. dummy), "
+                          f"low-rank-32 sigmoid relevance, e_k=1/log2(k+1), "
+                          f"eps={float(inst.eps):.4g}, T={T} Sinkhorn iterations per outer step, "
+                          f"N={N} Adam outer steps (lr=0.1 eps) from C=0, plans X stored in "
+                          f"BF16, FP32 Sinkhorn ({fform} forward {fk}, {bform} reverse sweep "
+                          f"{bk}), FP64 impacts and log-NSW",
+              "step": "one outer step of Algorithm 1 on all 100000 consumers: T-iteration "
+                      "forward, impacts, log-NSW, reverse sweep, Adam update; the timed call "
+                      "also runs the final forward that writes the BF16 plan of its last C",
+              "cells": cells, "cell_iters_per_step": cells * T,
+              "outer_steps_total": N, "eps": float(inst.eps), "T": T}
+    out = base_record(args, value, ms_per_step, config)
+    roof["solve_frac"] = value / roof["solve_ceiling_cell_iters_per_s"]
+    out.update({"nsw": nsw, "kernels": kernels, "roofline": roof, "metrics": metrics,
+                "paper_context": PAPER_CONTEXT})
+    if rest > 0:
+        out["solve"] = {"outer_steps": steps_done, "seconds": float(sum(seg_s)),
+                        "segments_s": seg_s,
+                        "note": f"the {steps_done}-step trajectory from C=0 in "
+                                f"{len(seg_s)} fr_solve calls (each ends with a forward; "
+                                f"{len(seg_s) - 1} more forwards than one call)",
+                        "cell_iters_per_s": cells * T * steps_done / float(sum(seg_s))}
+    if plain is not None:
+        out["plain_gpu"] = plain
+    if not args.skip_diag:
+        out["measured_peaks"] = measured_peaks(lib)
+    if not args.skip_cpu:
+        out["cpu_baseline"], _ = cpu_baseline_solve(inst, "C5", lr)
+    ctx.close()
+    return out
 
 
 CPU_SECONDS = 10.0   # oracle work per CPU baseline, roughly
@@ -544,8 +768,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
-    ap.add_argument("--outer", type=int, default=2, help="outer steps of the C5 solve")
+    ap.add_argument("--workload", default="C5", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--skip-rest", action="store_true",
+                    help="C5: stop after the timed steps (no complete 50-step trajectory)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -561,11 +786,10 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the consumer-sharded multi-GPU design is described, not built).", flush=True)
         sys.exit(2)
-    heavy = args.workload in ("C4", "C5")
     if args.steps is None:
-        args.steps = 1 if heavy else 5
+        args.steps = {"C4": 1, "C5": 20}.get(args.workload, 5)
     if args.warmup is None:
-        args.warmup = 0 if heavy else 1
+        args.warmup = {"C4": 0, "C5": 5}.get(args.workload, 1)
 
     import torch
     import paper_2406_10262_amd as fr
@@ -589,6 +813,8 @@ def main():
         out = bench_grad(args, fr, lib, dev)
     elif args.workload == "C4":
         out = bench_batched(args, fr, lib, dev)
+    elif args.workload == "C5":
+        out = bench_c5(args, fr, lib, dev)
     else:
         out = bench_solve(args, fr, lib, dev, args.workload)
     if out is not None:

@@ -337,14 +337,20 @@ def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF
 
 
 def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, start_step, K,
-           want_X, x_dtype, plain, grad_tol=0.0, sinkhorn_tol=0.0, cg_iters=0):
+           want_X, x_dtype, plain, grad_tol=0.0, sinkhorn_tol=0.0, cg_iters=0, inplace=False):
     U, I, m = prob.U, prob.I, prob.m
     dev = ctx.device
-    C = torch.zeros((U, I, m), dtype=torch.float32, device=dev) if C0 is None else C0.clone()
+
+    def own(t):   # the caller's tensor itself (inplace) or a copy
+        return t if inplace else t.clone()
+
+    C = torch.zeros((U, I, m), dtype=torch.float32, device=dev) if C0 is None else own(C0)
     _f32(C, (U, I, m), "C")
     if rule == "adam":
-        mom = torch.zeros_like(C) if mom is None else mom.clone()
-        vel = torch.zeros_like(C) if vel is None else vel.clone()
+        mom = torch.zeros_like(C) if mom is None else own(mom)
+        vel = torch.zeros_like(C) if vel is None else own(vel)
+        _f32(mom, (U, I, m), "mom")
+        _f32(vel, (U, I, m), "vel")
     else:
         mom = vel = None
     X = None
@@ -376,14 +382,18 @@ def _solve(fn, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel, sta
 def solve(ctx: Context, prob: Problem, N: int, lr: float, rule: str = "adam", beta1: float = 0.9,
           beta2: float = 0.999, adam_eps: float = 1e-8, C0=None, mom=None, vel=None,
           start_step: int = 0, K: int = 0, want_X: bool = True, x_dtype: str = "f32",
-          grad_tol: float = 0.0, sinkhorn_tol: float = 0.0, cg_iters: int = 0):
+          grad_tol: float = 0.0, sinkhorn_tol: float = 0.0, cg_iters: int = 0,
+          inplace: bool = False):
     """fr_solve: Algorithm 1 with at most N ascent steps (captured as a HIP
     graph); grad_tol = t > 0 ends the loop at the first ||dF/dC||_F <= t;
     sinkhorn_tol > 0 selects the converged-map form (warm starts, tolerance,
     implicit gradients).  The result's "updates" counts the updates applied,
-    "sinkhorn_iters" the Sinkhorn iterations of the converged-map form."""
+    "sinkhorn_iters" the Sinkhorn iterations of the converged-map form.
+    With inplace=True the given C0, mom and vel are updated in place (a
+    trajectory continued from start_step without copying its state)."""
     return _solve(load().fr_solve, ctx, prob, N, lr, rule, beta1, beta2, adam_eps, C0, mom, vel,
-                  start_step, K, want_X, x_dtype, False, grad_tol, sinkhorn_tol, cg_iters)
+                  start_step, K, want_X, x_dtype, False, grad_tol, sinkhorn_tol, cg_iters,
+                  inplace)
 
 
 def grad_converged(ctx: Context, prob: Problem, C: torch.Tensor, sinkhorn_tol: float,

@@ -11,6 +11,8 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    config.addinivalue_line("markers", "perf: timing comparison on the GPU, not a parity test "
+                                       "(not marked gpu; run with -m perf)")
 
 
 def gpu_available() -> bool:

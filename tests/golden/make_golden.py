@@ -22,8 +22,16 @@ the GPU library.
                      the oracle's impacts and F of the sub-instance and the
                      plans of two of its consumers; and Algorithm 1 (Adam,
                      lr 0.1 eps) for 3 steps from C = 0: F_0..F_3.
+  c5_traj.npz        the same sub-instance solved by Algorithm 1 for all 50
+                     outer steps (Adam, lr 0.1 eps, T 300, C0 = 0): F_0..F_50
+                     and the final impacts.  About an hour on 8 cores.
+  c4_full.npz        eight instances of the 128-instance batched workload (the
+                     four with the fewest plan cells and four drawn with seed
+                     44 from the rest) solved by Algorithm 1 at the configured
+                     size (eps 0.03, T 200, N 50, Adam lr 0.1 eps): F_0..F_50
+                     and the final impacts of each.
 
-Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3] [c5]
+Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3] [c5] [c5traj] [c4]
 """
 import json
 import os
@@ -177,6 +185,49 @@ def c5():
                         adam_F_hist=res["F_hist"], adam_imp=res["imp"])
 
 
+def c5traj():
+    inst, users, r = c5_subsample()
+    eps = float(inst.eps)
+    t0 = time.time()
+    res = oracle.solve(r.astype(np.float64), inst.e.astype(np.float64), eps, inst.T, inst.N,
+                       lr=float(inst.lr))
+    dt = time.time() - t0
+    print("c5traj", dt, res["F_hist"][0], res["F_hist"][-1], flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_traj.npz"), users=users, F_hist=res["F_hist"],
+                        imp_final=res["imp"], seconds=np.array([dt]),
+                        threads=np.array([oracle.num_threads()]))
+
+
+def c4_golden_instances():
+    """Indices of the batched workload's instances with stored oracle solves:
+    the four with the fewest plan cells and four drawn (seed 44) from the rest."""
+    shapes = W.batched_shapes(128, seed=4)
+    cells = np.array([a * b * c for a, b, c in shapes])
+    order = np.argsort(cells, kind="stable")
+    small = [int(j) for j in order[:4]]
+    rest = [int(j) for j in order[4:]]
+    rng = np.random.default_rng(44)
+    pick = sorted(int(j) for j in rng.choice(rest, 4, replace=False))
+    return shapes, small + pick
+
+
+def c4():
+    shapes, idx = c4_golden_instances()
+    out = {"idx": np.array(idx)}
+    for j in idx:
+        x = W.batched_instance(j, shapes[j])
+        t0 = time.time()
+        res = oracle.solve(x.r.astype(np.float64), x.e.astype(np.float64), float(x.eps), x.T,
+                           x.N, lr=float(x.lr))
+        dt = time.time() - t0
+        print("c4", j, shapes[j], dt, res["F_hist"][-1], flush=True)
+        out[f"F_hist_{j}"] = res["F_hist"]
+        out[f"imp_{j}"] = res["imp"]
+        out[f"seconds_{j}"] = np.array([dt])
+        # written after every instance so that a cut-off run keeps what it finished
+        np.savez_compressed(os.path.join(HERE, "c4_full.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["tiny"]
     if "tiny" in which:
@@ -187,3 +238,7 @@ if __name__ == "__main__":
         c3()
     if "c5" in which:
         c5()
+    if "c5traj" in which:
+        c5traj()
+    if "c4" in which:
+        c4()

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import workloads as W
-from gpu_util import F_REL, device_problem, f_err
+from gpu_util import F_REL, X_ABS, check_forward_at_own_C, device_problem, f_err
 
 pytestmark = pytest.mark.gpu
 
@@ -70,24 +70,25 @@ def test_batched_log_form_equals_single_instance_solver(fr):
 
 @pytest.mark.parametrize("j", [0, 3, 7, 12, 13])
 def test_batched_adam_objective_matches_oracle(fr, adam_run, j):
-    """Under Adam the plan itself is ill-conditioned (entries whose exact
-    gradient is ~0 take sign-like steps from rounding noise); the objective
-    and the impacts are not."""
+    """F history against the oracle's Adam trajectory, and the forward at the
+    GPU's own final C (plan, impacts and F).  Under Adam the trajectory itself
+    is ill-conditioned (entries whose exact gradient is ~0 take sign-like
+    steps from rounding noise), so plans and impacts are compared where they
+    are well conditioned: at identical C."""
     insts, probs, res, ctx = adam_run
     x = insts[j]
     print(f"case oracle Adam instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
     ref = oracle.solve(x.r, x.e, float(x.eps), x.T, 6, lr=0.003)
     Fb = res[j]["F_hist"].cpu().numpy()
     assert f_err(Fb, ref["F_hist"], x.I) <= F_REL
-    # individual impacts inherit the plan's sign-noise (~1e-4 after a few
-    # steps); F, a sum of their logs, stays within 1e-6.  A gross error in
-    # one item's impact would still show here.
-    imp, _ = fr.nsw(ctx, probs[j], res[j]["X"])
-    assert np.max(np.abs(imp.cpu().numpy() / ref["imp"] - 1)) <= 1e-3
+    check_forward_at_own_C(fr, ctx, probs[j], x.r, x.e, x.eps, x.T, res[j]["C"],
+                           X=res[j]["X"], F=Fb[-1])
 
 
 @pytest.mark.parametrize("j", [0, 7, 12])
 def test_batched_gradient_ascent_matches_oracle(fr, j):
+    """Plain ascent is well conditioned: costs and plans follow the oracle's
+    trajectory to the single-instance bars."""
     insts = _instances()
     ctx = fr.Context(0)
     _pin_launch(ctx, insts)
@@ -97,16 +98,15 @@ def test_batched_gradient_ascent_matches_oracle(fr, j):
     print(f"case oracle GD instance {j} U={x.U} I={x.I} m={x.m}", flush=True)
     ref = oracle.solve(x.r, x.e, float(x.eps), x.T, 4, rule="gd", lr=0.5)
     assert f_err(res[j]["F_hist"].cpu().numpy(), ref["F_hist"], x.I) <= F_REL
-    # C_4 = C_0 + lr sum_n grad_n: per-step gradients within GRAD_REL = 1e-4 of
-    # their maximum bound C to ~1e-4 of max |C_4|
     C = res[j]["C"].double().cpu().numpy()
     Cref = ref["C"]
-    assert np.max(np.abs(C - Cref)) <= 1e-4 * np.max(np.abs(Cref))
-    # the plan is exact to the forward bar at the GPU's own C_4, and follows the
-    # oracle's trajectory to the plan's sensitivity to that cost error
+    cerr = float(np.max(np.abs(C - Cref)) / np.max(np.abs(Cref)))
     X = res[j]["X"].double().cpu().numpy()
-    assert np.max(np.abs(X - oracle.forward(C, float(x.eps), x.T))) <= 1e-5
-    assert np.max(np.abs(X - ref["X"])) <= 1e-4
+    xerr = float(np.max(np.abs(X - ref["X"])))
+    print(f"  C error {cerr:.3e} of max |C|, X error {xerr:.3e}", flush=True)
+    check_forward_at_own_C(fr, ctx, probs[j], x.r, x.e, x.eps, x.T, res[j]["C"], X=res[j]["X"])
+    assert cerr <= 1e-5, cerr
+    assert xerr <= X_ABS, xerr
 
 
 def test_batched_ignores_team_widths_that_do_not_tile_its_blocks(fr):

@@ -1,17 +1,22 @@
 """Precision at scale: 1000 consumers sampled from the 100000 x 1000 x 50
 workload (eps 0.01, T 300), plans stored in BF16, FP64 impacts and log-NSW,
-against the FP64 oracle's stored values (tests/golden/c5_sub.npz)."""
+against the FP64 oracle's stored values (tests/golden/c5_sub.npz, and the
+50-step trajectory in tests/golden/c5_traj.npz)."""
 import os
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads as W
-from gpu_util import F_REL, IMP_REL, X_ABS, device_problem
+from gpu_util import F_REL, IMP_REL, X_ABS, device_problem, f_err
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c5_sub.npz")
+TRAJ = os.path.join(os.path.dirname(__file__), "golden", "c5_traj.npz")
+# BF16 storage rounds each plan entry to nearest even: relative error <= 2^-9.
+BF16_REL = 2.0 ** -9
 
 
 @pytest.fixture(scope="module")
@@ -46,3 +51,52 @@ def test_subsample_solve_bf16(fr, sub):
     res = fr.solve(ctx, prob, 3, float(inst.lr), x_dtype="bf16")
     Fh = res["F_hist"].cpu().numpy()
     assert np.max(np.abs(Fh / g["adam_F_hist"] - 1)) <= F_REL
+
+
+def test_subsample_bf16_plan_objective(fr, sub):
+    """Impacts and F of the stored BF16 plan (fr_nsw on X in BF16, FP64 sums)
+    against the oracle's FP64 plan.  Every entry carries at most 2^-9 relative
+    rounding, so every Imp_i (a positive combination of entries) is within
+    2^-9 plus the FP32 bar, and F = sum log Imp_i within I (2^-9 + IMP_REL)
+    absolutely, i.e. that relative to max(|F|, I).  The measured errors are
+    printed: rounding to nearest even averages far below the bound."""
+    g, inst, ctx, prob = sub
+    print("case C5 subsample BF16 plan impacts", flush=True)
+    C = torch.from_numpy(W.random_costs(1000, inst.I, inst.m, 2 * float(inst.eps), seed=56)).cuda()
+    out = fr.step(ctx, prob, C, want_X=True, x_dtype="bf16")
+    imp16, F16 = fr.nsw(ctx, prob, out["X"])
+    ierr = float(np.max(np.abs(imp16.cpu().numpy() / g["rand_imp"] - 1)))
+    ferr = f_err(float(F16.cpu()[0]), float(g["rand_F"][0]), inst.I)
+    print(f"  BF16 plan: Imp rel err {ierr:.3e}, F err {ferr:.3e} (bound {BF16_REL:.3e})",
+          flush=True)
+    assert ierr <= BF16_REL + IMP_REL
+    assert ferr <= BF16_REL + IMP_REL
+
+
+@pytest.mark.skipif(not os.path.exists(TRAJ), reason="tests/golden/c5_traj.npz not written")
+def test_subsample_trajectory_50_steps(fr, sub):
+    """Algorithm 1 for all 50 outer steps on the sub-instance (Adam, BF16
+    plans) against the oracle's FP64 trajectory; then the forward at the GPU's
+    own C_50: impacts and F of the FP32 path over all 1000 consumers, the
+    BF16 plans of 8 sampled consumers."""
+    g, inst, ctx, prob = sub
+    t = np.load(TRAJ)
+    N = int(t["F_hist"].shape[0]) - 1
+    print(f"case C5 subsample {N}-step solve", flush=True)
+    res = fr.solve(ctx, prob, N, float(inst.lr), x_dtype="bf16")
+    Fh = res["F_hist"].cpu().numpy()
+    assert f_err(Fh, t["F_hist"], inst.I) <= F_REL
+    print("  oracle forward at the GPU's C_50", flush=True)
+    users = g["users"]
+    C = res["C"]
+    out = fr.step(ctx, prob, C)
+    Cn = C.double().cpu().numpy()
+    Xr = oracle.forward(Cn, float(inst.eps), inst.T)
+    imp_r = oracle.impact(inst.r[users], inst.e, Xr)
+    ierr = float(np.max(np.abs(out["imp"].cpu().numpy() / imp_r - 1)))
+    print(f"  impacts at own C: {ierr:.3e}", flush=True)
+    assert ierr <= IMP_REL
+    assert f_err(Fh[-1], oracle.nsw(imp_r), inst.I) <= F_REL
+    sel = np.sort(np.random.default_rng(58).choice(1000, 8, replace=False))
+    X = res["X"][torch.from_numpy(sel).long().cuda()].float().cpu().numpy()
+    assert np.all(np.abs(X - Xr[sel]) <= 2.0 ** -8 * np.abs(Xr[sel]) + X_ABS)
