@@ -151,10 +151,11 @@ fr_status fr_workspace_bytes(const fr_problem* prob, const fr_optim* optim, size
 fr_status fr_workspace_init(fr_ctx* ctx, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- forward */
-/Section 3 + Eqs. Imp, objF: X_u = Sinkhorn_T(C_u) for every consumer (T
+/* Section 3 + Eqs. Imp, objF: X_u = Sinkhorn_T(C_u) for every consumer (T
  * iterations from g = 0, each a row then a column half-step; computed in the
  * scaling form with log-domain absorption by default, or in the log domain
- * after fr_ctx_set_form -- the same iterates), then Imp and F.  C [U][I][m] float.  Outputs, each optional (NULL = not written):
+ * after fr_ctx_set_form -- the same iterates), then Imp and F.  C [U][I][m]
+ * float.  Outputs, each optional (NULL = not written):
  * X [U][I][m] in x_dtype (BF16 rounds to nearest even; the impacts are always
  * taken from the FP32 plan), pot [U][I+m] float potentials f then g in cost
  * units, imp [I] double, F [1] double.  Impacts are summed over consumers in
