@@ -164,6 +164,26 @@ fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
                   fr_dtype x_dtype, float* pot, double* imp, double* F,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* fr_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as fr_step, with no workspace argument.  The
+ * workspace fr_step would take (header, impacts, impact partials, the per-row
+ * impact contributions) lives in a device array that the library holds on
+ * every GPU it runs on, 64 MiB, which limits the problem to about
+ * |U| |I| <= 14.9 million (precisely: the bytes fr_step needs before its
+ * history, 4 |U| |I| + 8 |I| ceil(|U|/16) + 8 |I| + 256, rounded up per part
+ * to 256).  Larger problems return FR_E_WORKSPACE before anything is
+ * enqueued.  imp [I] and F [1] are required here (FR_E_NULL otherwise): the
+ * device conditions fr_sync_status reports for fr_step are not reported for
+ * this call; an impact <= 0 or non-finite shows as a non-finite F.  The call
+ * allocates nothing (no hipMalloc, no library allocation).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams or threads without ordering between them) race and their results
+ * are undefined.  FR_E_DEVICE if the array's address could not be resolved
+ * when the context was created. */
+fr_status fr_step_noalloc(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
+                          fr_dtype x_dtype, float* pot, double* imp, double* F, void* stream);
+
 /* Eqs. Imp and objF for a given plan X [U][I][m] (x_dtype): imp [I] and F [1]
  * (double, either optional).  X need not be a Sinkhorn output. */
 fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype,

@@ -35,7 +35,39 @@ struct fr_ctx {
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
     size_t max_lds = 64 * 1024;                           // LDS a block may use on the device
+    void* scratch = nullptr;   // device address of this device's fr_step_noalloc array
 };
+
+// Device memory of fr_step_noalloc, for callers that cannot allocate: the
+// workspace fr_step takes from its caller (header, impacts, impact partials,
+// the per-row impact contributions y) lives here instead, up to
+// kScratchBytes.  Every GPU the library runs on holds one copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the device (scratch_address), never
+// through the array's name.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kScratchDevices] = {};
+
+// The device address of `scratch` on `device`, resolved once per device (the
+// device must be current).  nullptr if the runtime cannot resolve it.
+void* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_addr[device] = ptr;
+        else (void)hipGetLastError();   // leave no sticky error for the caller's next call
+    }
+    return g_scratch_addr[device];
+}
+}  // namespace
 
 namespace {
 
@@ -651,6 +683,7 @@ fr_status fr_ctx_create(int device, fr_ctx** out) {
         delete c;
         return FR_E_DEVICE;
     }
+    c->scratch = scratch_address(device);   // fr_step_noalloc reports FR_E_DEVICE if null
     (void)registry();
     *out = c;
     return FR_OK;
@@ -717,22 +750,21 @@ fr_status fr_get_launch(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m
     return FR_OK;
 }
 
-fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X, fr_dtype x_dtype,
-                  float* pot, double* imp, double* F, void* ws, size_t ws_bytes, void* stream) {
-    if (!ctx) return FR_E_NULL;
-    fr_status st = check_problem(prob);
-    if (st) return st;
-    if (!C || !ws) return FR_E_NULL;
-    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+}  // extern "C"
+
+namespace {
+// fr_step on a given workspace w of at least layout(prob, 1).hist bytes;
+// clear_header: reset the header first (its flags are sticky otherwise).
+fr_status step_on(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X, fr_dtype x_dtype,
+                  float* pot, double* imp, double* F, char* w, bool clear_header, void* stream) {
     const Layout Lw = layout(prob, 1);
-    // fr_step needs everything but the history
-    if (ws_bytes < Lw.hist) return FR_E_WORKSPACE;
     Shape sh;
+    fr_status st;
     if ((st = make_shape(ctx, prob->n_users, prob->n_items, prob->m, 1, &sh))) return st;
     FR_TRY(hipSetDevice(ctx->device));
     hipStream_t s = pick_stream(ctx, stream);
-    char* w = (char*)ws;
     WsHeader* hdr = (WsHeader*)(w + Lw.hdr);
+    if (clear_header) hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, hdr, (int64_t)0);
     FwdArgs a = fwd_args(prob, sh, C);
     a.y = (float*)(w + Lw.y);
     a.X = X;
@@ -743,6 +775,33 @@ fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X, 
                   imp ? imp : (double*)(w + Lw.imp), F, nullptr, 0, hdr, 0, s);
     FR_TRY(hipGetLastError());
     return FR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fr_status fr_step(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X, fr_dtype x_dtype,
+                  float* pot, double* imp, double* F, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !ws) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    // fr_step needs everything but the history
+    if (ws_bytes < layout(prob, 1).hist) return FR_E_WORKSPACE;
+    return step_on(ctx, prob, C, X, x_dtype, pot, imp, F, (char*)ws, false, stream);
+}
+
+fr_status fr_step_noalloc(fr_ctx* ctx, const fr_problem* prob, const float* C, void* X,
+                          fr_dtype x_dtype, float* pot, double* imp, double* F, void* stream) {
+    if (!ctx) return FR_E_NULL;
+    fr_status st = check_problem(prob);
+    if (st) return st;
+    if (!C || !imp || !F) return FR_E_NULL;
+    if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
+    if (layout(prob, 1).hist > kScratchBytes) return FR_E_WORKSPACE;
+    if (!ctx->scratch) return FR_E_DEVICE;
+    return step_on(ctx, prob, C, X, x_dtype, pot, imp, F, (char*)ctx->scratch, true, stream);
 }
 
 fr_status fr_nsw(fr_ctx* ctx, const fr_problem* prob, const void* X, fr_dtype x_dtype, double* imp,
