@@ -27,11 +27,13 @@ the GPU library.
                      and the final impacts.  About an hour on 8 cores.
   c4_full.npz        eight instances of the 128-instance batched workload (the
                      four with the fewest plan cells and four drawn with seed
-                     44 from the rest) solved by Algorithm 1 at the configured
+                     44 from the rest of those with at most 1e7 plan cells)
+                     solved by Algorithm 1 at the configured
                      size (eps 0.03, T 200, N 50, Adam lr 0.1 eps): F_0..F_50
                      and the final impacts of each.
 
-Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3] [c5] [c5traj] [c4]
+Usage:  python tests/golden/make_golden.py [tiny] [c2] [c3] [c5] [c5traj]
+        python tests/golden/make_golden.py c4 [instance ...] [--out DIR]
 """
 import json
 import os
@@ -198,34 +200,64 @@ def c5traj():
                         threads=np.array([oracle.num_threads()]))
 
 
+def _solve_in_chunks(r, e, eps, T, N, lr, tag, chunk=5):
+    """oracle.solve for N outer steps, resumed every `chunk` steps (the
+    oracle's resume is bitwise) so that progress is printed as it goes."""
+    res = None
+    F = []
+    done = 0
+    while done < N:
+        n = min(chunk, N - done)
+        if res is None:
+            res = oracle.solve(r, e, eps, T, n, lr=lr)
+        else:
+            res = oracle.solve(r, e, eps, T, n, C0=res["C"], lr=lr, mom=res["mom"],
+                               vel=res["vel"], start_step=done)
+        F.extend(res["F_hist"][(0 if done == 0 else 1):].tolist())
+        done += n
+        print(f"  {tag}: {done}/{N} outer steps", flush=True)
+    res["F_hist"] = np.array(F)
+    return res
+
+
 def c4_golden_instances():
     """Indices of the batched workload's instances with stored oracle solves:
-    the four with the fewest plan cells and four drawn (seed 44) from the rest."""
+    the four with the fewest plan cells and four drawn (seed 44) from the rest
+    of those with at most 1e7 plan cells (an FP64 oracle solve of 50 outer
+    steps of a larger one takes longer than a run may)."""
     shapes = W.batched_shapes(128, seed=4)
     cells = np.array([a * b * c for a, b, c in shapes])
     order = np.argsort(cells, kind="stable")
     small = [int(j) for j in order[:4]]
-    rest = [int(j) for j in order[4:]]
+    rest = [int(j) for j in order[4:] if cells[j] <= 10_000_000]
     rng = np.random.default_rng(44)
     pick = sorted(int(j) for j in rng.choice(rest, 4, replace=False))
     return shapes, small + pick
 
 
-def c4():
+def c4(only=None, out_dir=HERE):
+    """Oracle solves of the stored batched instances; with ``only`` (instance
+    indices) just those, merged into the file's existing entries.  The file is
+    rewritten after every instance, so a cut-off run keeps what it finished."""
     shapes, idx = c4_golden_instances()
+    path = os.path.join(out_dir, "c4_full.npz")
     out = {"idx": np.array(idx)}
-    for j in idx:
+    if os.path.exists(path):
+        old = np.load(path)
+        out.update({k: old[k] for k in old.files if k != "idx"})
+    todo = [j for j in idx if only is None or j in only]
+    for j in todo:
         x = W.batched_instance(j, shapes[j])
         t0 = time.time()
-        res = oracle.solve(x.r.astype(np.float64), x.e.astype(np.float64), float(x.eps), x.T,
-                           x.N, lr=float(x.lr))
+        res = _solve_in_chunks(x.r.astype(np.float64), x.e.astype(np.float64), float(x.eps),
+                               x.T, x.N, float(x.lr), f"c4 instance {j} {shapes[j]}")
         dt = time.time() - t0
         print("c4", j, shapes[j], dt, res["F_hist"][-1], flush=True)
         out[f"F_hist_{j}"] = res["F_hist"]
         out[f"imp_{j}"] = res["imp"]
         out[f"seconds_{j}"] = np.array([dt])
-        # written after every instance so that a cut-off run keeps what it finished
-        np.savez_compressed(os.path.join(HERE, "c4_full.npz"), **out)
+        out[f"threads_{j}"] = np.array([oracle.num_threads()])
+        np.savez_compressed(path, **out)
 
 
 if __name__ == "__main__":
@@ -241,4 +273,11 @@ if __name__ == "__main__":
     if "c5traj" in which:
         c5traj()
     if "c4" in which:
-        c4()
+        # optional: c4 <j> <j> ... [--out DIR]
+        rest = which[which.index("c4") + 1:]
+        out_dir = HERE
+        if "--out" in rest:
+            out_dir = rest[rest.index("--out") + 1]
+            rest = rest[:rest.index("--out")]
+        only = [int(a) for a in rest if a.isdigit()] or None
+        c4(only, out_dir)
