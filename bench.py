@@ -53,11 +53,14 @@ LDS_PEAK = CUS * 128 * CLOCK                       # 128 B per clock per CU: 78.
 #     (two FMAs on K and the column scalings), the column adjoint
 #     sum_i P_ik fbar_i (FMA) and the cost adjoint cbar += P (gh + fbar)
 #     (two FMAs): 10 flops (log domain: plus one exponential).
-FWD_FLOPS = {"log": 4, "scaling": 4}
-BWD_FLOPS = {"log": 10, "scaling": 10}
-FWD_TRANS = {"log": 1, "scaling": 0}
-BWD_TRANS = {"log": 1, "scaling": 0}
-FORMS = {0: "log", 1: "scaling"}
+# The tile kernels of large plans compute the scaling form (their reverse
+# sweep's cost-adjoint FMAs run as an FP32 matrix-core contraction, whose
+# published dense peak is also 157.3 TFLOP/s).
+FWD_FLOPS = {"log": 4, "scaling": 4, "tile": 4}
+BWD_FLOPS = {"log": 10, "scaling": 10, "tile": 10}
+FWD_TRANS = {"log": 1, "scaling": 0, "tile": 0}
+BWD_TRANS = {"log": 1, "scaling": 0, "tile": 0}
+FORMS = {0: "log", 1: "scaling", 2: "tile"}
 HBM_PEAK = 8.0e12
 # The paper's own speed statements (Section 4.2 and the footnote of Section
 # 4.1), on an NVIDIA GeForce RTX 3090 against an Intel Core i9-12900K; no
@@ -117,10 +120,13 @@ def kernel_names(lib, ctx, prob):
     lib.fr_ctx_kernel_forms(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(ff),
                             ctypes.byref(bf))
     fform, bform = FORMS[ff.value], FORMS[bf.value]
-    fk = "k_fwds" if fform == "scaling" else "k_fwd"
+    fk = {"scaling": "k_fwds", "log": "k_fwd", "tile": "k_tfwd"}[fform]
     nl = ctypes.c_int32()
     lib.fr_ctx_bwd_lds_rows(ctx.handle, prob.U, prob.I, prob.m, 0, ctypes.byref(nl))
-    bk = "k_bwds" if bform == "scaling" else ("k_bwdl" if nl.value > 0 else "k_bwd")
+    if bform == "tile":
+        bk = "k_tbwd+k_tgrad"   # reverse sweep, then the factor contraction with Adam
+    else:
+        bk = "k_bwds" if bform == "scaling" else ("k_bwdl" if nl.value > 0 else "k_bwd")
     return fk, fform, bk, bform
 
 

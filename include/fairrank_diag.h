@@ -27,7 +27,9 @@ fr_status fr_ctx_kernel_times(fr_ctx* ctx, double* fwd_ms, int64_t* fwd_launches
 /* The arithmetic form (FR_FORM_LOG or FR_FORM_SCALING) of the fused forward
  * and reverse sweep that fr_solve runs on this context for a problem of this
  * shape with checkpoint interval K (0 = every iterate), at the launch shape
- * fr_get_launch reports.  Host pointers, each optional. */
+ * fr_get_launch reports; 2 for the scaling form on the tile kernels of large
+ * plans (launch shape reported as 512 lanes, 0 rows).  Host pointers, each
+ * optional. */
 fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
                               int32_t checkpoint_every, int32_t* fwd_form, int32_t* bwd_form);
 

@@ -41,7 +41,8 @@ def _units():
     for mp in MP_CLASSES:
         units.append((os.path.join(CSRC, "fr_fused.hip"), os.path.join(BUILD, f"fr_fused_{mp}.o"),
                       [f"-DFR_MP={mp}"]))
-    for name in ("fr_reduce", "fr_plain", "fr_metrics", "fr_baselines", "fr_diag", "fr_api"):
+    for name in ("fr_tile", "fr_reduce", "fr_plain", "fr_metrics", "fr_baselines", "fr_diag",
+                 "fr_api"):
         src = os.path.join(CSRC, name + ".hip")
         if os.path.exists(src):
             units.append((src, os.path.join(BUILD, name + ".o"), []))

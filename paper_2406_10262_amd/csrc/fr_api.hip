@@ -164,6 +164,8 @@ struct Shape {
     int L, R, mp, block, teams, grid;
     size_t lds_fwd, lds_bwd;
     size_t lds_cb;       // part of lds_bwd holding cost adjoints (reverse sweep fe->bwdl only)
+    const TileEntry* te; // tile kernels run the forward (and the reverse sweep if tile_bwd)
+    bool tile_bwd;
 };
 
 // Issue model of one Sinkhorn iteration (forward and backward) of U consumers
@@ -227,7 +229,15 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
     if (mp < 0) return FR_E_UNSUPPORTED;
     std::pair<int, int> lr;
     auto it = ctx->launch.find({I, m});
-    lr = (it != ctx->launch.end()) ? it->second : default_launch(U, I, m);
+    const bool pinned = it != ctx->launch.end();
+    lr = pinned ? it->second : default_launch(U, I, m);
+    // the tile kernels (scaling form): the default for the plans they take,
+    // or a launch pinned as (512 lanes, 0 rows)
+    const TileEntry* te = tile_entry(m, I);
+    const bool want_tile = te && ctx->form == FR_FORM_SCALING &&
+                           (pinned ? lr.second == 0 : true);
+    if (pinned && lr.second == 0 && !want_tile) return FR_E_UNSUPPORTED;
+    if (want_tile && lr.second == 0) lr = default_launch(U, I, m);
     const int L = lr.first, R = lr.second;
     if (L == 0) return FR_E_UNSUPPORTED;   // more rows than any instantiated kernel holds
     if (!lanes_ok(L) || (int64_t)L * R < I) return FR_E_PARAM;
@@ -258,6 +268,12 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
             sh->lds_cb = cb;
         }
     }
+    sh->te = want_tile ? te : nullptr;
+    sh->tile_bwd = want_tile && K <= 1;
+    if (want_tile) {
+        sh->fwd = te->fwd;
+        if (K <= 1) sh->bwd = te->bwd;
+    }
     sh->absorb = ctx->absorb;
     sh->L = L;
     sh->R = R;
@@ -272,8 +288,10 @@ fr_status make_shape(fr_ctx* ctx, int64_t U, int I, int m, int K, Shape* sh) {
 
 // ---------------------------------------------------------------- workspace
 struct Layout {
-    size_t hdr, imp, partial, y, hist, grad, gpart, gw, phi, total;
+    size_t hdr, imp, partial, y, hist, grad, gpart, gw, phi, tile, total;
     int nchunk, nck, hs;
+    size_t tile_stride;    // bytes per consumer of the tile reverse sweep's buffer (0: none)
+    int64_t tile_batch;    // consumers per batch
 };
 
 int n_checkpoints(int T, int K) { return (T + K - 1) / K + 1; }
@@ -312,6 +330,18 @@ Layout layout(const fr_problem* p, int K, bool tol = false, bool conv = false) {
         off += align_up(sizeof(float) * (size_t)U * L.hs);
         L.phi = off;
         off += align_up(sizeof(float) * (size_t)U * I);
+    }
+    // the tile reverse sweep's factors, for the plans the tile kernels take
+    // (whichever kernels a context then picks)
+    L.tile = off;
+    L.tile_stride = 0;
+    L.tile_batch = 0;
+    if (K <= 1 && !conv) {
+        if (const TileEntry* te = tile_entry(p->m, I)) {
+            L.tile_stride = tile_consumer_bytes(te, p->sinkhorn_iters);
+            L.tile_batch = std::min<int64_t>(U, kTileBatch);
+            off += align_up(L.tile_stride * (size_t)L.tile_batch);
+        }
     }
     L.total = off;
     return L;
@@ -420,6 +450,14 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     return a;
 }
 
+// The tile reverse sweep's buffer and the flag word, from the workspace.
+void attach_tile(BwdArgs& b, const Layout& Lw, char* w) {
+    b.tile.base = w + Lw.tile;
+    b.tile.stride = Lw.tile_stride;
+    b.tile.batch = Lw.tile_batch;
+    b.flags = &((WsHeader*)(w + Lw.hdr))->flags;
+}
+
 fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
     sh.fwd(a, sh.grid, sh.block, sh.lds_fwd, s);
     FR_TRY(hipGetLastError());
@@ -427,6 +465,8 @@ fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
 }
 
 fr_status launch_bwd(const Shape& sh, const BwdArgs& a, hipStream_t s) {
+    if (sh.tile_bwd && (!a.tile.base || a.tile.stride == 0 || a.tile.batch < 1))
+        return FR_E_WORKSPACE;
     sh.bwd(a, sh.grid, sh.block, sh.lds_bwd, s);
     FR_TRY(hipGetLastError());
     return FR_OK;
@@ -471,6 +511,7 @@ fr_status read_flags(WsHeader* h, hipStream_t s, bool clear) {
     }
     if (fl & FLAG_NONFINITE) return FR_E_NONFINITE;
     if (fl & FLAG_ZERO_IMPACT) return FR_E_ZERO_IMPACT;
+    if (fl & FLAG_EPOCHS) return FR_E_UNSUPPORTED;
     return FR_OK;
 }
 
@@ -728,6 +769,11 @@ fr_status fr_workspace_init(fr_ctx* ctx, void* ws, size_t ws_bytes, void* stream
 fr_status fr_set_launch(fr_ctx* ctx, int32_t n_items, int32_t m, int32_t lanes, int32_t rows) {
     if (!ctx) return FR_E_NULL;
     if (n_items < 2 || m < 2 || m > n_items || m > kMaxM || n_items > kMaxItems) return FR_E_SHAPE;
+    if (lanes == 512 && rows == 0) {   // the tile kernels
+        if (!tile_entry(m, n_items)) return FR_E_UNSUPPORTED;
+        ctx->launch[{n_items, m}] = {512, 0};
+        return FR_OK;
+    }
     if (!lanes_ok(lanes) || rows < 1 || (int64_t)lanes * rows < n_items) return FR_E_PARAM;
     const Registry& reg = registry();
     const int mp = reg.mp_for(m);
@@ -744,6 +790,9 @@ fr_status fr_get_launch(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m
     if (n_users < 1) return FR_E_SHAPE;
     std::pair<int, int> lr =
         (it != ctx->launch.end()) ? it->second : default_launch(n_users, n_items, m);
+    if (tile_entry(m, n_items) && ctx->form == FR_FORM_SCALING &&
+        (it == ctx->launch.end() || lr.second == 0))
+        lr = {512, 0};   // the tile kernels
     if (lr.first == 0) return FR_E_UNSUPPORTED;
     *lanes = lr.first;
     *rows = lr.second;
@@ -923,6 +972,7 @@ fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const
     b.gF = gF;
     b.dC = dC;
     b.dr = dr;
+    attach_tile(b, Lw, w);
     return launch_bwd(sh, b, s);
 }
 
@@ -966,6 +1016,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     b.K = K;
     b.nck = Lw.nck;
     b.imp = imp;
+    attach_tile(b, Lw, w);
     b.Cw = C;
     b.mom = adam_m;
     b.vel = adam_v;
@@ -1180,8 +1231,10 @@ fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int
     Shape sh;
     fr_status st = make_shape(ctx, n_users, n_items, m, resolve_k(checkpoint_every), &sh);
     if (st) return st;
-    if (fwd_form) *fwd_form = (sh.fwd == sh.fe->fwds) ? FR_FORM_SCALING : FR_FORM_LOG;
-    if (bwd_form) *bwd_form = (sh.bwd == sh.fe->bwds) ? FR_FORM_SCALING : FR_FORM_LOG;
+    if (fwd_form)
+        *fwd_form = sh.te ? 2 : (sh.fwd == sh.fe->fwds) ? FR_FORM_SCALING : FR_FORM_LOG;
+    if (bwd_form)
+        *bwd_form = sh.tile_bwd ? 2 : (sh.bwd == sh.fe->bwds) ? FR_FORM_SCALING : FR_FORM_LOG;
     return FR_OK;
 }
 
@@ -1523,6 +1576,10 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
     hipEvent_t e0 = evs.ev[0], e1 = evs.ev[1];
     float best = 1e30f;
     std::pair<int, int> best_lr{0, 0};
+    // candidates: the tile kernels where they take the plan, then every
+    // instantiated (lanes, rows per lane) shape
+    std::vector<std::pair<int, int>> cands;
+    if (!batched && tile_entry(p.m, I) && ctx->form == FR_FORM_SCALING) cands.push_back({512, 0});
     const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024};
     for (int L : Ls) {
         if (batched && (L > 256 || 256 % L != 0)) continue;
@@ -1532,10 +1589,17 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             if ((int64_t)L * R < I || (int64_t)L * (R - 1) >= I) continue;
             if (&e != reg.pick(mp, R, L, batched ? 256 : block_for(L))) continue;
             if (batched && R * mp > 128) continue;
+            cands.push_back({L, R});
+        }
+    }
+    for (const auto& lr : cands) {
+        {
+            const int L = lr.first, R = lr.second;
             ctx->launch[{I, p.m}] = {L, R};
             Shape sh;
             if (make_shape(ctx, p.n_users, I, p.m, 1, &sh) != FR_OK) continue;
-            if (sh.fe != &e) continue;
+            if (R > 0 && (sh.te || sh.fe != reg.pick(mp, R, L, batched ? 256 : block_for(L))))
+                continue;
             FwdArgs a = fwd_args(&p, sh, C);
             a.y = (float*)(w + Lw.y);
             a.hist = (float*)(w + Lw.hist);
@@ -1545,6 +1609,8 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             b.nck = Lw.nck;
             double* impw = (double*)(w + Lw.imp);
             b.imp = impw;
+            attach_tile(b, Lw, w);
+            if (sh.tile_bwd && Lw.tile_stride == 0) continue;
             // one warm-up repetition, then the fastest of three
             float tot = 1e30f;
             for (int rep = 0; rep < 4; ++rep) {

@@ -7,7 +7,7 @@
 namespace fr {
 
 // Device-side flag bits written into the workspace header.
-enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_ZERO_IMPACT = 2u };
+enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_ZERO_IMPACT = 2u, FLAG_EPOCHS = 4u };
 
 // Workspace header (first 256 bytes of every workspace).
 struct WsHeader {
@@ -44,6 +44,16 @@ struct FwdArgs {
     float eps_ln2;         // eps ln 2: base-2 potential -> cost units
 };
 
+// Buffer of the tile reverse sweep (fr_tile.hip): per consumer of a batch,
+// the row and column factors of every iteration and the reference kernels.
+struct TileBuf {
+    char* base;        // batch consumers x stride bytes
+    size_t stride;     // bytes per consumer
+    int64_t batch;     // consumers per batch
+};
+// Reference rebases of the tile reverse sweep kept per consumer.
+constexpr int kTileEpochs = 16;
+
 struct BwdArgs {
     const float* C;        // [U][I][m] cost (read)
     const float* r;        // [U][I]
@@ -63,6 +73,8 @@ struct BwdArgs {
     int absorb;               // scaling-form sweep: also rebase every `absorb` iterations
     float cg_tol;             // implicit form: relative residual to stop at
     int64_t step_const;
+    TileBuf tile;             // tile reverse sweep: factor buffer (fr_tile.hip)
+    uint32_t* flags;          // device flag word (FLAG_EPOCHS), or null
     double gF;
     int64_t U;
     int I, m, T, K, nck, hs, L, rule;
@@ -116,6 +128,18 @@ FR_MP_CLASSES(FR_DECL_ENTRIES)
 
 // Reverse-sweep block length when every iterate is kept (K == 1).
 constexpr int kLoadBlock = 32;
+
+// Tile kernels for large plans (fr_tile.hip): one consumer per block of 512
+// lanes, plans of imin < I <= imax rows and m <= cmax columns, scaling form.
+struct TileEntry {
+    int cmax, imax, imin;
+    FwdLaunch fwd;   // grid and block arguments ignored: one block per consumer
+    BwdLaunch bwd;   // every iterate kept (K = 1); uses BwdArgs::tile
+};
+const TileEntry* tile_entry(int m, int I);
+size_t tile_consumer_bytes(const TileEntry* e, int T);
+// Consumers per batch of the tile reverse sweep.
+constexpr int64_t kTileBatch = 6144;
 
 // Reductions over consumers (fr_reduce.hip).  F_hist[hdr->rep] receives F;
 // advance: 0 leaves the counters, ADV_REP advances rep, ADV_REP_STEP rep and

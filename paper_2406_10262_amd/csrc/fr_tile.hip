@@ -1,0 +1,872 @@
+// fr_tile.hip -- Sinkhorn forward and adjoint backward of Algorithm 1 for
+// large plans (hundreds of items, tens of positions per consumer) on gfx950.
+//
+// Mapping.  One block of 64 W lanes owns one consumer.  The plan is cut into
+// 2-D tiles: lanes are grouped in quads (G = 4 lanes, a DPP quad), the quad
+// of lane l is row group rg = 16 w + l / 4 of the block (w its wave), and
+// lane l % 4 of the quad (its column group cg) holds the CT consecutive
+// columns cg CT .. cg CT + CT - 1 of the RT rows i = j RG + rg (j < RT,
+// RG = 16 W row groups).  A row half-step of Sinkhorn (Section 3, problem
+// otp) is then a lane-local sum over CT columns and a two-step DPP sum over
+// the quad; a column half-step is a lane-local sum over RT rows, a sum over
+// the 16 quads of a wave (two DPP rotations inside each 16-lane row and the
+// two gfx950 row swaps across rows) and a sum of the W wave partials through
+// LDS, one barrier per half-step.
+//
+// Forward (k_tfwd).  Scaling form with log-domain absorption, the same
+// iterates as the log-domain recursion: registers hold the kernel
+//   Kt_ik = 2^(a_ik + gam_k + ph_i),  a_ik = -c_ik / (eps ln 2) - o_i,
+// (o_i the row maximum at load) and an iteration updates the scalings only,
+//   u_i = 1 / sum_k Kt_ik v_k,   v_k = b_k / sum_i Kt_ik u_i,
+// with b = (1, ..., 1, I - m + 1) (the dummy column, Section 2).  When a
+// column scaling leaves [2^-32, 2^32] (or every `absorb` iterations) the
+// scalings move into (gam, ph) and Kt is rebuilt from C.  The base-2 column
+// potentials gamma^t = gam + log2 v^t are kept for the reverse sweep.
+//
+// Backward.  The reverse sweep of the T iterations ("chain rule", Section 3)
+// is the recursion of the log-domain kernels: with P^t the row-normalised
+// plan of iteration t and gh_k = gbar_k / sig^t_k,
+//   fbar_i = [t = T] fbar0_i - sum_k P_ik gh_k,
+//   cbar_ik += P_ik (gh_k + fbar_i),   gbar_k <- -sum_i P_ik fbar_i,
+// started from X and G = dF/dX (Eqs. Imp, objF).  Within a stretch of
+// iterations that share one reference kernel Kt = 2^(a + rho + phi),
+// P^t_ik = Kt_ik w_k u_i with w_k = 2^(gamma^{t-1}_k - rho_k) and
+// u_i = 1 / sum_k Kt_ik w_k, so each iteration adds a rank-two matrix times
+// Kt to the cost adjoint:
+//   cbar_ik += Kt_ik [u_i (w_k gh_k) + (u_i fbar_i) w_k].
+// The sweep (k_tbwd) therefore never holds cost adjoints: per iteration it
+// forms the row sums sum_k Kt w and sum_k Kt w gh (quad sums), the column sum
+// sum_i Kt (u fbar), and stores the row factors (u, u fbar) and column
+// factors (w gh, w).  k_tgrad then contracts them over the iterations on the
+// matrix cores (FP32 MFMA, 32 x 32 x 2 tiles), multiplies by the reference
+// kernel of each stretch, and applies the update (Adam / ascent) or writes
+// dF/dC.  The initial term -G X / eps at t = T has the same form and is the
+// last slot of the contraction.  A reference is rebased (a new stretch) when
+// a column's w leaves [2^-32, 2^32]; at most kTileEpochs stretches per
+// consumer are stored, beyond which the sweep raises FLAG_EPOCHS.
+#include <type_traits>
+
+#include "fr_device.h"
+#include "fr_internal.h"
+
+namespace fr {
+namespace {
+
+constexpr float kScaleHi = 4294967296.0f;         // 2^32
+constexpr float kScaleLo = 1.0f / 4294967296.0f;  // 2^-32
+constexpr float kTiny = 1.17549435e-38f;
+
+// DPP row rotations (GFX9 encoding): lane p of a 16-lane row reads lane
+// (p + n) mod 16.
+constexpr int kRowRor4 = 0x124;
+constexpr int kRowRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_max(float v) {
+    return fmaxf(v, dpp_mov<CTRL>(v));
+}
+
+// Sum over the four lanes of a quad (symmetric: every lane gets the same
+// rounded value).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += dpp_mov<kQuadXor1>(v);
+    v += dpp_mov<kQuadXor2>(v);
+    return v;
+}
+__device__ __forceinline__ float quad_max(float v) {
+    v = dpp_max<kQuadXor1>(v);
+    v = dpp_max<kQuadXor2>(v);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Column reduction of a wave.  p[c] (c < CT) holds the lane's partial sum of
+// column cg CT + c over its rows.  Step A adds the four quads of each 16-lane
+// row (rotations by 4 and 8, which keep the column group); step B adds the
+// four rows with the two row swaps as a reduce-scatter: after it, lane
+// 16 rho + cg + 4 q holds in z[q] the wave's sum of column slot
+// slot(rho, q) of column group cg (valid where slot_ok).  Only the lanes of
+// quad position 0 (q index of the lane, l & 12 == 0) are the wave's writers:
+// the other three lanes of the row hold the same sums in another rounding
+// order.
+template <int CT>
+struct Slots {
+    static constexpr int H1 = (CT + 1) / 2;
+    static constexpr int H2 = (H1 + 1) / 2;
+    // column slot of z[q] in 16-lane row rho
+    static constexpr int slot(int rho, int q) {
+        return q + ((rho & 1) ? H2 : 0) + ((rho & 2) ? H1 : 0);
+    }
+    static constexpr bool ok(int rho, int q) {
+        return q < ((rho & 1) ? H1 - H2 : H2) && slot(rho, q) < CT;
+    }
+};
+
+template <int CT>
+__device__ __forceinline__ void wave_colsum(float (&p)[CT], float (&z)[Slots<CT>::H2]) {
+    constexpr int H1 = Slots<CT>::H1, H2 = Slots<CT>::H2;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) p[c] += dpp_mov<kRowRor4>(p[c]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) p[c] += dpp_mov<kRowRor8>(p[c]);
+    __builtin_amdgcn_sched_barrier(0);
+    unsigned x[H1], y[H1];
+#pragma unroll
+    for (int c = 0; c < H1; ++c) {
+        x[c] = __builtin_bit_cast(unsigned, p[c]);
+        y[c] = (c + H1 < CT) ? __builtin_bit_cast(unsigned, p[c + H1]) : 0u;
+    }
+    swap32_batch<H1>(x, y);
+    float h[H1];
+#pragma unroll
+    for (int c = 0; c < H1; ++c) h[c] = __builtin_bit_cast(float, x[c]) + __builtin_bit_cast(float, y[c]);
+    unsigned x2[H2], y2[H2];
+#pragma unroll
+    for (int c = 0; c < H2; ++c) {
+        x2[c] = __builtin_bit_cast(unsigned, h[c]);
+        y2[c] = (c + H2 < H1) ? __builtin_bit_cast(unsigned, h[c + H2]) : 0u;
+    }
+    swap16_batch<H2>(x2, y2);
+#pragma unroll
+    for (int c = 0; c < H2; ++c) z[c] = __builtin_bit_cast(float, x2[c]) + __builtin_bit_cast(float, y2[c]);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Lane roles of a block.
+template <int CT, int W>
+struct TLane {
+    int l, w, cg, rg, rho, q;   // lane, wave, column group, row group, 16-lane row, quad position
+    bool writer;                // holds the wave's column sums (q == 0)
+    int rcol;                   // column this lane reduces across waves (or -1)
+    int rslot;                  // its slot in the column group (cg * 16 + slot)
+    __device__ __forceinline__ TLane() {
+        const int tid = threadIdx.x;
+        l = tid & 63;
+        w = tid >> 6;
+        cg = l & 3;
+        rg = w * 16 + (l >> 2);
+        rho = l >> 4;
+        q = (l >> 2) & 3;
+        writer = q == 0;
+        rcol = -1;
+        rslot = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq)
+                if (r == rho && qq == q && Slots<CT>::ok(r, qq)) {
+                    rslot = cg * 16 + Slots<CT>::slot(r, qq);
+                    rcol = cg * CT + Slots<CT>::slot(r, qq);
+                }
+    }
+};
+
+// Writers put the wave's column sums in part[par][slot][w] (W floats per slot).
+template <int CT, int W>
+__device__ __forceinline__ void put_partials(const TLane<CT, W>& t, const float (&z)[Slots<CT>::H2],
+                                             float* part) {
+    if (!t.writer) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r != t.rho) continue;
+#pragma unroll
+        for (int qq = 0; qq < Slots<CT>::H2; ++qq)
+            if (Slots<CT>::ok(r, qq)) part[(t.cg * 16 + Slots<CT>::slot(r, qq)) * W + t.w] = z[qq];
+    }
+}
+
+// Team total of the lane's reduced column, summed in wave order (identical in
+// every wave).  Call after the barrier that follows put_partials.
+template <int CT, int W>
+__device__ __forceinline__ float team_total(const TLane<CT, W>& t, const float* part) {
+    if (t.rcol < 0) return 0.f;
+    const float* src = part + t.rslot * W;
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += src[w];
+    return s;
+}
+
+// Per-wave broadcast: the reducing lanes write nv values of their column
+// (vb[v][slot]), every lane then reads the values of its CT columns.
+__device__ __forceinline__ void lds_wave_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <int CT, int NV>
+__device__ __forceinline__ void spread_cols(float* vb, int rslot, bool has, const float (&val)[NV],
+                                            int cg, float (&out)[NV][CT]) {
+    if (has) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) vb[v * 64 + rslot] = val[v];
+    }
+    lds_wave_fence();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) out[v][c] = vb[v * 64 + cg * 16 + c];
+    lds_wave_fence();
+}
+
+// LDS of one block: column partials (2 parities x 64 slots x W), per-wave
+// broadcast areas (W x 4 x 64), and the potentials of a block of iterations.
+template <int W>
+constexpr size_t tile_lds_floats(bool bwd) {
+    return 2 * 64 * W + W * 4 * 64 + (bwd ? (kLoadBlock + 1) * 64 : 0);
+}
+
+// Loads are unconditional from clamped, in-bounds addresses (a padded row
+// reads row 0, a padded column the row's last column), and padding is made
+// harmless arithmetically: padded columns carry the potential kNeg and rows
+// beyond I the offset kBig, so that their kernel entries 2^(...) are exactly
+// 0.  No per-cell condition stays live across the iterations.
+constexpr float kBig = 1.0e30f;
+
+__device__ __forceinline__ float opaque_f(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ int opaque_s(int x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// Scaled costs of the lane's cells: a = c c2 - o_i, with o_i the row maximum
+// of c c2 over the real columns (quad max); padded columns -> about kNeg,
+// rows beyond I -> offset kBig.
+template <int CT, int RT, int W>
+__device__ __forceinline__ void tile_load(const float* C, int64_t u, int I, int m, float c2,
+                                          const TLane<CT, W>& t, float (&a)[RT][CT],
+                                          float (&off)[RT], float (&om)[RT]) {
+    constexpr int RG = 16 * W;
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        const bool valid = i < I;
+        const float* src = C + (u * I + (valid ? i : 0)) * (int64_t)m;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int k = t.cg * CT + c;
+            a[j][c] = src[k < m ? k : m - 1];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        float mx = kNeg;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int k = t.cg * CT + c;
+            a[j][c] = (k < m) ? a[j][c] * c2 : kNeg;
+            mx = fmaxf(mx, a[j][c]);
+        }
+        mx = quad_max(mx);
+        const bool valid = i < I;
+        off[j] = valid ? mx : kBig;
+        om[j] = valid ? 1.f : 0.f;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) a[j][c] -= off[j];
+    }
+}
+
+// Kt = 2^(a + gam + ph) from the costs in HBM (a = c c2 - off); gam is kNeg
+// on padded columns.
+template <int CT, int RT, int W>
+__device__ __forceinline__ void tile_rebuild(const float* C, int64_t u, int I, int m, float c2,
+                                             const TLane<CT, W>& t, const float (&off)[RT],
+                                             const float (&gam)[CT], const float (&ph)[RT],
+                                             float (&kt)[RT][CT]) {
+    constexpr int RG = 16 * W;
+    const int Io = opaque_s(I), mo = opaque_s(m);
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        const float* src = C + (u * Io + (i < Io ? i : 0)) * (int64_t)mo;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int k = t.cg * CT + c;
+            kt[j][c] = src[k < mo ? k : mo - 1];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) kt[j][c] = ex2((fmaf(kt[j][c], c2, -off[j]) + gam[c]) + ph[j]);
+}
+
+// ---------------------------------------------------------------------------
+template <int CT, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    constexpr int RG = 16 * W;
+    const TLane<CT, W> t;
+    const int64_t u = blockIdx.x;
+    const int I = a.I, m = a.m;
+    float* part = smem;                      // [2][64][W]
+    float* vb = smem + 2 * 64 * W + t.w * 256;   // this wave's [4][64]
+
+    float kt[RT][CT], off[RT], om[RT];
+    tile_load<CT, RT, W>(a.C, u, I, m, a.c2, t, kt, off, om);
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) kt[j][c] = ex2(kt[j][c]);   // gam = 0, ph = 0
+
+    // the reducing lane's column: b, scaling, absorbed potential
+    const bool live = t.rcol >= 0 && t.rcol < m;
+    const float bk = live ? ((t.rcol == m - 1) ? (float)(I - m + 1) : 1.f) : 0.f;
+    float vd = live ? 1.f : 0.f, gd = live ? 0.f : kNeg;
+    float v[CT], gam[CT];
+    {
+        float val[2] = {vd, gd}, out[2][CT];
+        spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            v[c] = out[0][c];
+            gam[c] = out[1][c];
+        }
+    }
+    float ph[RT], us[RT];
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        ph[j] = 0.f;
+        us[j] = 1.f;
+    }
+    float* hist = a.hist ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
+    auto put_hist = [&](float* dst) {
+        if (t.w == 0 && t.rcol >= 0 && t.rcol < a.hs) dst[t.rcol] = fmaxf(gd + lg2(vd), kNeg);
+    };
+    if (hist) put_hist(hist);
+
+    for (int it = 1; it <= a.T; ++it) {
+        // row half-step: u_i = 1 / sum_k Kt_ik v_k
+        float wj[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            float ps[2] = {0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < CT; ++c) ps[c & 1] = fmaf(kt[j][c], v[c], ps[c & 1]);
+            const float s = quad_sum(ps[0] + ps[1]);
+            us[j] = (om[j] > 0.f) ? rcp(s) : 0.f;
+            wj[j] = us[j];
+        }
+        // column half-step: v_k = b_k / sum_i Kt_ik u_i
+        float p[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < RT; ++j) acc = fmaf(kt[j][c], wj[j], acc);
+            p[c] = acc;
+        }
+        float z[Slots<CT>::H2];
+        wave_colsum<CT>(p, z);
+        float* pp = part + (it & 1) * 64 * W;
+        put_partials<CT, W>(t, z, pp);
+        __syncthreads();
+        const float tot = team_total<CT, W>(t, pp);
+        vd = live ? bk * rcp(fmaxf(tot, kTiny)) : 0.f;
+        const bool bad = __builtin_amdgcn_ballot_w64(live && !(vd >= kScaleLo && vd <= kScaleHi)) != 0;
+        if (bad || (a.absorb > 0 && it % a.absorb == 0)) {
+            // absorb the scalings into the potentials; rebuild Kt (log-domain step)
+            if (live) gd += lg2(vd);
+            vd = live ? 1.f : 0.f;
+#pragma unroll
+            for (int j = 0; j < RT; ++j) {
+                ph[j] += (om[j] > 0.f) ? lg2(us[j]) : 0.f;
+                us[j] = 1.f;
+            }
+            float val[2] = {vd, gd}, out[2][CT];
+            spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                v[c] = out[0][c];
+                gam[c] = out[1][c];
+            }
+            tile_rebuild<CT, RT, W>(a.C, u, I, m, a.c2, t, off, gam, ph, kt);
+        } else {
+            float val[1] = {vd}, out[1][CT];
+            spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) v[c] = out[0][c];
+        }
+        if (hist) {
+            if (it % a.K == 0)
+                put_hist(hist + (int64_t)(it / a.K) * a.hs);
+            else if (it == a.T)
+                put_hist(hist + (int64_t)(a.nck - 1) * a.hs);
+        }
+    }
+
+    // epilogue: X = Kt v u, y_i = r_i sum_{k < m-1} e_k x_ik, potentials
+    const int mo = m;
+    float ek[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const int k = t.cg * CT + c;
+        ek[c] = (k < mo - 1) ? a.e[k] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        const bool valid = i < I;
+        const int64_t row = u * I + (valid ? i : 0);
+        float yy = 0.f;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int k = t.cg * CT + c;
+            const float x = (kt[j][c] * v[c]) * us[j];
+            yy = fmaf(ek[c], x, yy);
+            if (a.X && valid && k < mo) {
+                if (a.x_bf16)
+                    ((uint16_t*)a.X)[row * mo + k] = to_bf16(x);
+                else
+                    ((float*)a.X)[row * mo + k] = x;
+            }
+        }
+        yy = quad_sum(yy);
+        if (valid && t.cg == 0) {
+            if (a.y) a.y[row] = a.r[row] * yy;
+            const float phi = ph[j] + lg2(us[j]) - off[j];
+            if (a.pot) a.pot[u * (int64_t)(I + mo) + i] = phi * a.eps_ln2;
+        }
+    }
+    if (a.pot && t.w == 0 && live) a.pot[u * (int64_t)(I + mo) + I + t.rcol] = (gd + lg2(vd)) * a.eps_ln2;
+}
+
+// ---------------------------------------------------------------------------
+// Per-consumer area of the tile buffer (TileBuf in fr_internal.h).
+struct TileView {
+    float* A;     // [T+1][2][IP]  row factors per iteration (slot T: initial term)
+    float* B;     // [T+1][2][64]  column factors
+    float* rho;   // [kTileEpochs][64]  reference column potentials
+    float* phi;   // [kTileEpochs][IP]  reference row offsets
+    float* off;   // [IP]  row centring offsets of the scaled costs
+    int* ep;      // [kTileEpochs + 1]: ep[0] = number of stretches, ep[1 + e] = first t of stretch e
+};
+
+__device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int T, int IP) {
+    char* base = tb.base + b * tb.stride;
+    TileView v;
+    size_t o = 0;
+    v.A = (float*)(base + o);
+    o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
+    v.B = (float*)(base + o);
+    o += sizeof(float) * (size_t)(T + 1) * 2 * 64;
+    v.rho = (float*)(base + o);
+    o += sizeof(float) * (size_t)kTileEpochs * 64;
+    v.phi = (float*)(base + o);
+    o += sizeof(float) * (size_t)kTileEpochs * IP;
+    v.off = (float*)(base + o);
+    o += sizeof(float) * (size_t)IP;
+    v.ep = (int*)(base + o);
+    return v;
+}
+
+// Reference kernel of a new stretch: Kt = 2^(a + rho + phi), phi_i putting
+// each row's largest entry at 1 (quad max of a + rho); rho is kNeg on padded
+// columns, off kBig on rows beyond I (phi 0 there).
+template <int CT, int RT, int W>
+__device__ __forceinline__ void tile_reference(const float* C, int64_t u, int I, int m, float c2,
+                                               const TLane<CT, W>& t, const float (&off)[RT],
+                                               const float (&rho)[CT], float (&phr)[RT],
+                                               float (&kt)[RT][CT]) {
+    constexpr int RG = 16 * W;
+    const int Io = opaque_s(I), mo = opaque_s(m);
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        const float* src = C + (u * Io + (i < Io ? i : 0)) * (int64_t)mo;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int k = t.cg * CT + c;
+            kt[j][c] = src[k < mo ? k : mo - 1];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        float mx = kNeg;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            kt[j][c] = fmaf(kt[j][c], c2, -off[j]) + rho[c];
+            mx = fmaxf(mx, kt[j][c]);
+        }
+        mx = quad_max(mx);
+        phr[j] = (i < Io) ? -mx : 0.f;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) kt[j][c] = ex2(kt[j][c] + phr[j]);
+    }
+}
+
+template <int CT, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+    extern __shared__ float smem[];
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    constexpr int RG = 16 * W;
+    constexpr int IP = RT * RG;
+    const TLane<CT, W> t;
+    const int b = blockIdx.x;
+    if (b >= nb) return;
+    const int64_t u = u0 + b;
+    const int I = a.I, m = a.m, T = a.T;
+    float* part = smem;                          // [2][64][W]
+    float* vb = smem + 2 * 64 * W + t.w * 256;   // this wave's [4][64]
+    float* seg = smem + 2 * 64 * W + W * 256;    // [kLoadBlock + 1][64]
+    const TileView tv = tile_view(tb, b, T, IP);
+    const float* hist = a.hist + u * (int64_t)a.nck * a.hs;
+    const int hs = a.hs;
+
+    float kt[RT][CT], off[RT], om[RT];
+    tile_load<CT, RT, W>(a.C, u, I, m, a.c2, t, kt, off, om);
+    float rg[RT];   // gF r_i / Imp_i
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        const int i = j * RG + t.rg;
+        rg[j] = (i < I) ? (float)(a.gF * (double)a.r[u * I + i] / a.imp[i]) : 0.f;
+        if (t.cg == 0) tv.off[i] = off[j];
+    }
+
+    // the reducing lane's column
+    const bool live = t.rcol >= 0 && t.rcol < m;
+    const float ibc = live ? ((t.rcol == m - 1) ? 1.f / (float)(I - m + 1) : 1.f) : 0.f;
+    const float ekd = (live && t.rcol < m - 1) ? a.e[t.rcol] : 0.f;
+    float gbar = 0.f, rhod = 0.f;
+
+    // segment of potentials gamma^{t0} .. gamma^{t1} in LDS (every iterate kept)
+    int seg_t0 = -1;
+    auto load_seg = [&](int tt) {   // block containing gamma^{tt-1}, gamma^{tt}
+        const int t0 = ((tt - 1) / kLoadBlock) * kLoadBlock;
+        if (t0 == seg_t0) return;
+        __syncthreads();
+        const int n = min(kLoadBlock, T - t0);
+        for (int idx = threadIdx.x; idx < (n + 1) * 64; idx += blockDim.x) {
+            const int qq = idx >> 6, k = idx & 63;
+            seg[idx] = (k < hs) ? hist[(int64_t)(t0 + qq) * hs + k] : kNeg;
+        }
+        __syncthreads();
+        seg_t0 = t0;
+    };
+    auto gam_at = [&](int tt) { return seg[(tt - seg_t0) * 64 + (t.rcol >= 0 ? t.rcol : 0)]; };
+
+    // first stretch: reference rho = gamma^{T-1}
+    int ne = 0;
+    float phr[RT];
+    auto new_stretch = [&](int tt) {
+        float val[1] = {live ? rhod : kNeg}, out[1][CT];
+        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        tile_reference<CT, RT, W>(a.C, u, I, m, a.c2, t, off, out[0], phr, kt);
+        const int e = ne < kTileEpochs ? ne : kTileEpochs - 1;
+        if (ne >= kTileEpochs && threadIdx.x == 0) atomicOr(a.flags, FLAG_EPOCHS);
+        if (t.w == 0 && t.rcol >= 0) tv.rho[e * 64 + t.rcol] = live ? rhod : 0.f;
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+            if (t.cg == 0) tv.phi[e * IP + j * RG + t.rg] = phr[j];
+        if (threadIdx.x == 0) tv.ep[1 + e] = tt;
+        ne = (ne < kTileEpochs) ? ne + 1 : ne;
+    };
+    load_seg(T);
+    rhod = live ? gam_at(T - 1) : 0.f;
+    new_stretch(T);
+
+    // initial term (t = T): X = P^T diag(b / sig^T); cbar = -G X / eps
+    float fb0[RT];
+    {
+        const float gp = live ? gam_at(T - 1) : kNeg, gq = live ? gam_at(T) : kNeg;
+        const float wd = live ? ex2(gp - rhod) : 0.f;
+        const float xr = live ? ex2(gq - gp) : 0.f;
+        const float ev = ekd * wd * xr;
+        float val[2] = {wd, ev}, out[2][CT];
+        spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        float qr[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            float s = 0.f, xe = 0.f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                s = fmaf(kt[j][c], out[0][c], s);
+                xe = fmaf(kt[j][c], out[1][c], xe);
+            }
+            s = quad_sum(s);
+            xe = quad_sum(xe);
+            const float qj = (om[j] > 0.f) ? a.inv_eps * rcp(s) : 0.f;   // 1 / (eps s_i)
+            const float xs = qj * xe;                                   // sum_k e_k x_ik / eps
+            fb0[j] = rg[j] * xs;
+            qr[j] = rg[j] * qj;
+            const int i = j * RG + t.rg;
+            if (t.cg == 0) {
+                tv.A[(size_t)(T * 2 + 0) * IP + i] = -qr[j];
+                tv.A[(size_t)(T * 2 + 1) * IP + i] = 0.f;
+                if (a.dr && i < I) a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * (xs / a.inv_eps);
+            }
+        }
+        if (t.w == 0 && t.rcol >= 0) {
+            tv.B[(size_t)(T * 2 + 0) * 64 + t.rcol] = ev;
+            tv.B[(size_t)(T * 2 + 1) * 64 + t.rcol] = 0.f;
+        }
+        float p[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < RT; ++j) acc = fmaf(kt[j][c], qr[j], acc);
+            p[c] = acc;
+        }
+        float z[Slots<CT>::H2];
+        wave_colsum<CT>(p, z);
+        put_partials<CT, W>(t, z, part);
+        __syncthreads();
+        gbar = ev * team_total<CT, W>(t, part);
+    }
+
+    // reverse sweep t = T .. 1
+    int par = 1;
+    for (int tt = T; tt >= 1; --tt) {
+        load_seg(tt);
+        const float gp = live ? gam_at(tt - 1) : kNeg, gq = live ? gam_at(tt) : kNeg;
+        float wd = live ? ex2(gp - rhod) : 0.f;
+        const bool bad = __builtin_amdgcn_ballot_w64(live && !(wd >= kScaleLo && wd <= kScaleHi)) != 0;
+        if (bad || (a.absorb > 0 && tt < T && (T - tt) % a.absorb == 0)) {
+            rhod = live ? gp : 0.f;
+            new_stretch(tt);
+            wd = live ? 1.f : 0.f;
+        }
+        const float gh = live ? gbar * ex2(gq - gp) * ibc : 0.f;   // gbar / sig^t
+        const float wg = wd * gh;
+        float val[2] = {wd, wg}, out[2][CT];
+        spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        float aa[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+            float s = 0.f, d = 0.f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                s = fmaf(kt[j][c], out[0][c], s);
+                d = fmaf(kt[j][c], out[1][c], d);
+            }
+            s = quad_sum(s);
+            d = quad_sum(d);
+            const float uj = (om[j] > 0.f) ? rcp(s) : 0.f;
+            const float fb = (tt == T ? fb0[j] : 0.f) - uj * d;
+            aa[j] = uj * fb;
+            const int i = j * RG + t.rg;
+            if (t.cg == (j & 3)) {
+                tv.A[(size_t)((tt - 1) * 2 + 0) * IP + i] = uj;
+                tv.A[(size_t)((tt - 1) * 2 + 1) * IP + i] = aa[j];
+            }
+        }
+        if (t.w == 0 && t.rcol >= 0) {
+            tv.B[(size_t)((tt - 1) * 2 + 0) * 64 + t.rcol] = wg;
+            tv.B[(size_t)((tt - 1) * 2 + 1) * 64 + t.rcol] = wd;
+        }
+        float p[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < RT; ++j) acc = fmaf(kt[j][c], aa[j], acc);
+            p[c] = acc;
+        }
+        float z[Slots<CT>::H2];
+        wave_colsum<CT>(p, z);
+        float* pp = part + par * 64 * W;
+        put_partials<CT, W>(t, z, pp);
+        __syncthreads();
+        gbar = -wd * team_total<CT, W>(t, pp);
+        par ^= 1;
+    }
+    if (threadIdx.x == 0) tv.ep[0] = ne;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction of the sweep's factors.  Block (b, rb): 4 waves, wave v takes
+// the 32-row tile rt = 4 rb + v of consumer u0 + b and both 32-column tiles.
+// Result lane layout of v_mfma_f32_32x32x2f32 (checked on the device): lane l
+// holds D[row][l % 32] for row = (v % 4) + 8 (v / 4) + 4 (l / 32), v < 16; it
+// supplies A[l % 32][l / 32] and B[l / 32][l % 32].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int mfma_row(int v, int l) { return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5); }
+
+template <int IP>
+__global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    const int b = blockIdx.x;
+    if (b >= nb) return;
+    const int64_t u = u0 + b;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rt = blockIdx.y * 4 + wv;
+    const int I = a.I, m = a.m, T = a.T;
+    if (rt * 32 >= I) return;
+    const TileView tv = tile_view(tb, b, T, IP);
+    const int col = l & 31;
+    const int half = l >> 5;
+
+    // costs and row offsets of the lane's 32 output cells (clamped, in-bounds
+    // loads; rows beyond I carry the offset kBig, so their kernel is 0)
+    float cv[2][16], offr[16];
+    const int k0c = col < m ? col : m - 1, k1c = 32 + col < m ? 32 + col : m - 1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = rt * 32 + mfma_row(v, l);
+        offr[v] = tv.off[i];
+        const float* src = a.C + (u * I + (i < I ? i : I - 1)) * (int64_t)m;
+        cv[0][v] = src[k0c];
+        cv[1][v] = src[k1c];
+    }
+    float cb[2][16];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) cb[ct][v] = 0.f;
+
+    const int ne = min(tv.ep[0], kTileEpochs);
+    const float* Ap = tv.A + (size_t)half * IP + rt * 32 + col;   // + slot * 2 IP
+    const float* Bp = tv.B + (size_t)half * 64 + col;             // + slot * 128 (+ 32)
+    const bool c0ok = col < m, c1ok = 32 + col < m;
+    for (int e = 0; e < ne; ++e) {
+        const int hi = tv.ep[1 + e];                    // first (largest) t of the stretch
+        const int lo = (e + 1 < ne) ? tv.ep[2 + e] : 0; // first t of the next stretch
+        f32x16 acc0 = {}, acc1 = {};
+        // slots lo .. hi-1 (iterations lo+1 .. hi), and the initial term in stretch 0
+        const int s0 = lo, s1 = hi + (e == 0 ? 1 : 0);
+        int s = s0;
+        for (; s + 4 <= s1; s += 4) {
+            float av[4], bv0[4], bv1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int sl = (s + q == hi && e == 0) ? T : s + q;
+                av[q] = Ap[(size_t)sl * 2 * IP];
+                bv0[q] = Bp[(size_t)sl * 128];
+                bv1[q] = Bp[(size_t)sl * 128 + 32];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bv0[q] = c0ok ? bv0[q] : 0.f;
+                bv1[q] = c1ok ? bv1[q] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv0[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv1[q], acc1, 0, 0, 0);
+            }
+        }
+        for (; s < s1; ++s) {
+            const int sl = (s == hi && e == 0) ? T : s;
+            const float av = Ap[(size_t)sl * 2 * IP];
+            float bv0 = Bp[(size_t)sl * 128], bv1 = Bp[(size_t)sl * 128 + 32];
+            bv0 = c0ok ? bv0 : 0.f;
+            bv1 = c1ok ? bv1 : 0.f;
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv1, acc1, 0, 0, 0);
+        }
+        // times the stretch's reference kernel Kt = 2^(c c2 - off + rho + phi)
+        float rk0 = tv.rho[e * 64 + col], rk1 = tv.rho[e * 64 + 32 + col];
+        rk0 = c0ok ? rk0 : kNeg;
+        rk1 = c1ok ? rk1 : kNeg;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = rt * 32 + mfma_row(v, l);
+            const float ph = tv.phi[e * IP + i];
+            const float k0 = ex2((fmaf(cv[0][v], a.c2, -offr[v]) + rk0) + ph);
+            const float k1 = ex2((fmaf(cv[1][v], a.c2, -offr[v]) + rk1) + ph);
+            cb[0][v] = fmaf(k0, acc0[v], cb[0][v]);
+            cb[1][v] = fmaf(k1, acc1[v], cb[1][v]);
+        }
+    }
+
+    // gF dF/dC, or the ascent step on C (Adam's bias corrections from the step count)
+    float bc1 = 1.f, bc2 = 1.f;
+    if (a.Cw && a.rule == 0) {
+        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
+        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
+        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = rt * 32 + mfma_row(v, l);
+        if (i >= I) continue;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int k = ct * 32 + col;
+            if (k >= m) continue;
+            const int64_t idx = (u * I + i) * (int64_t)m + k;
+            const float g = cb[ct][v];
+            if (a.dC) a.dC[idx] = g;
+            if (a.Cw) {
+                const float craw = cv[ct][v];
+                if (a.rule == 0) {
+                    const float gl = -g;
+                    const float mo = a.b1 * a.mom[idx] + (1.f - a.b1) * gl;
+                    const float ve = a.b2 * a.vel[idx] + (1.f - a.b2) * gl * gl;
+                    a.mom[idx] = mo;
+                    a.vel[idx] = ve;
+                    a.Cw[idx] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
+                } else {
+                    a.Cw[idx] = craw + a.lr * g;
+                }
+            }
+        }
+    }
+}
+
+template <int CT, int RT, int W>
+void launch_tfwd(const FwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    (void)block;
+    (void)lds;
+    hipLaunchKernelGGL((k_tfwd<CT, RT, W>), dim3(grid), dim3(64 * W),
+                       tile_lds_floats<W>(false) * sizeof(float), s, a);
+}
+
+// The backward in batches of tb.batch consumers: the sweep writes the factors
+// of a batch into the tile buffer, the contraction consumes them.
+template <int CT, int RT, int W>
+void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+    (void)grid;
+    (void)block;
+    (void)lds;
+    constexpr int IP = RT * 16 * W;
+    const TileBuf& tb = a.tile;
+    for (int64_t u0 = 0; u0 < a.U; u0 += tb.batch) {
+        const int nb = (int)((a.U - u0) < tb.batch ? (a.U - u0) : tb.batch);
+        hipLaunchKernelGGL((k_tbwd<CT, RT, W>), dim3(nb), dim3(64 * W),
+                           tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
+        hipLaunchKernelGGL((k_tgrad<IP>), dim3(nb, (a.I + 127) / 128), dim3(256), 0, s, a, tb, u0,
+                           nb);
+    }
+}
+
+}  // namespace
+
+// Instantiated tile shapes: G = 4 lanes per row, CT columns per lane, RT rows
+// per lane, W waves per block.  13 columns per lane serve 40 <= m <= 50 (the
+// column classes 40, 48 and 50, whose potentials the forward writes in
+// full); 8 rows per lane over 128 row groups serve 512 < I <= 1024.
+struct TileShape {
+    int mmin;
+    TileEntry e;
+};
+static const TileShape kTileShapes[] = {
+    {40, {50, 8 * 16 * 8, 8 * 16 * 8 / 2, &launch_tfwd<13, 8, 8>, &launch_tbwd<13, 8, 8>}},
+};
+
+const TileEntry* tile_entry(int m, int I) {
+    for (const TileShape& t : kTileShapes)
+        if (m >= t.mmin && m <= t.e.cmax && I <= t.e.imax && I > t.e.imin) return &t.e;
+    return nullptr;
+}
+
+size_t tile_consumer_bytes(const TileEntry* e, int T) {
+    const size_t IP = (size_t)e->imax;
+    size_t o = 0;
+    o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
+    o += sizeof(float) * (size_t)(T + 1) * 2 * 64;
+    o += sizeof(float) * (size_t)kTileEpochs * 64;
+    o += sizeof(float) * (size_t)kTileEpochs * IP;
+    o += sizeof(float) * IP;
+    o += sizeof(int) * (size_t)(kTileEpochs + 1);
+    return (o + 255) / 256 * 256;
+}
+
+}  // namespace fr

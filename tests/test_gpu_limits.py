@@ -59,6 +59,11 @@ def test_wide_recompute_sweeps_keep_cost_adjoints_in_lds(fr, form):
     print(f"case lds rows form={form}", flush=True)
     ctx = fr.Context(0)
     ctx.set_form(form)
+    if form == "scaling":
+        # the 1000 x 50 plans run on the tile kernels in the scaling form
+        assert ctx.get_launch(100000, 1000, 50) == (512, 0)
+        assert _lds_rows(fr, ctx, 100000, 1000, 50) == 0
+        ctx.set_launch(1000, 50, 512, 2)
     assert ctx.get_launch(100000, 1000, 50) == (512, 2)
     assert _lds_rows(fr, ctx, 100000, 1000, 50) == 1
     assert _lds_rows(fr, ctx, 2000, 100, 10) == 0
