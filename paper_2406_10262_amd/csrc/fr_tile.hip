@@ -163,7 +163,8 @@ struct TLane {
     }
 };
 
-// Writers put the wave's column sums in part[par][slot][w] (W floats per slot).
+// Writers put the wave's column sums in part[w][slot] (64 slots per wave, so
+// that the lanes of one access touch consecutive words: no bank conflicts).
 template <int CT, int W>
 __device__ __forceinline__ void put_partials(const TLane<CT, W>& t, const float (&z)[Slots<CT>::H2],
                                              float* part) {
@@ -173,7 +174,7 @@ __device__ __forceinline__ void put_partials(const TLane<CT, W>& t, const float 
         if (r != t.rho) continue;
 #pragma unroll
         for (int qq = 0; qq < Slots<CT>::H2; ++qq)
-            if (Slots<CT>::ok(r, qq)) part[(t.cg * 16 + Slots<CT>::slot(r, qq)) * W + t.w] = z[qq];
+            if (Slots<CT>::ok(r, qq)) part[t.w * 64 + t.cg * 16 + Slots<CT>::slot(r, qq)] = z[qq];
     }
 }
 
@@ -182,10 +183,9 @@ __device__ __forceinline__ void put_partials(const TLane<CT, W>& t, const float 
 template <int CT, int W>
 __device__ __forceinline__ float team_total(const TLane<CT, W>& t, const float* part) {
     if (t.rcol < 0) return 0.f;
-    const float* src = part + t.rslot * W;
     float s = 0.f;
 #pragma unroll
-    for (int w = 0; w < W; ++w) s += src[w];
+    for (int w = 0; w < W; ++w) s += part[w * 64 + t.rslot];
     return s;
 }
 
@@ -229,6 +229,14 @@ __device__ __forceinline__ float opaque_f(float x) {
 __device__ __forceinline__ int opaque_s(int x) {
     asm volatile("" : "+s"(x));
     return x;
+}
+// A wave-uniform pointer the optimiser cannot see through: addresses formed
+// from it are computed where they are used instead of being hoisted (and
+// kept live, or spilled) across a loop.
+template <class P>
+__device__ __forceinline__ P* opaque_p(P* p) {
+    asm volatile("" : "+s"(p));
+    return p;
 }
 
 // Scaled costs of the lane's cells: a = c c2 - o_i, with o_i the row maximum
@@ -444,6 +452,7 @@ struct TileView {
     float* phi;   // [kTileEpochs][IP]  reference row offsets
     float* off;   // [IP]  row centring offsets of the scaled costs
     int* ep;      // [kTileEpochs + 1]: ep[0] = number of stretches, ep[1 + e] = first t of stretch e
+    float* cb;    // [IP][64]  running cost adjoint when a consumer has several stretches
 };
 
 __device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int T, int IP) {
@@ -461,6 +470,9 @@ __device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int 
     v.off = (float*)(base + o);
     o += sizeof(float) * (size_t)IP;
     v.ep = (int*)(base + o);
+    o += sizeof(int) * (size_t)(kTileEpochs + 1);
+    o = (o + 255) / 256 * 256;
+    v.cb = (float*)(base + o);
     return v;
 }
 
@@ -689,123 +701,145 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int mfma_row(int v, int l) { return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5); }
 
+// Operands of one slot for the wave's two row tiles (A) and two column tiles
+// (B), loaded raw; the MFMAs that use them mask padded columns to 0 and, for
+// a slot past the end of the stretch, A to 0 (its MFMAs then add exactly 0).
+// Masking at the use keeps the loads in flight until then.
+struct Opd {
+    float a0, a1, b0, b1;
+};
+
+template <int IP>
+__device__ __forceinline__ Opd load_opd(const float* Ap, const float* Bp, int sl) {
+    Opd o;
+    o.a0 = Ap[(size_t)sl * 2 * IP];
+    o.a1 = Ap[(size_t)sl * 2 * IP + 32];
+    o.b0 = Bp[(size_t)sl * 128];
+    o.b1 = Bp[(size_t)sl * 128 + 32];
+    return o;
+}
+
+// Block (b, rb): 4 waves; wave v takes the row tiles 2 (4 rb + v) and
+// 2 (4 rb + v) + 1 (64 rows) of consumer u0 + b and both 32-column tiles, so
+// each slot costs 4 MFMAs for 2 row and 2 column operand loads.  Operands are
+// loaded kPre slots ahead of the MFMAs that use them.
+constexpr int kPre = 6;
+
 template <int IP>
 __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
     if (a.stop && *a.stop) return;   // the outer loop has ended
     const int b = blockIdx.x;
     if (b >= nb) return;
     const int64_t u = u0 + b;
-    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int rt = blockIdx.y * 4 + wv;
+    const int l = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform in the wave
+    const int rt0 = (blockIdx.y * 4 + wv) * 2;
     const int I = a.I, m = a.m, T = a.T;
-    if (rt * 32 >= I) return;
+    if (rt0 * 32 >= I) return;
     const TileView tv = tile_view(tb, b, T, IP);
     const int col = l & 31;
     const int half = l >> 5;
-
-    // costs and row offsets of the lane's 32 output cells (clamped, in-bounds
-    // loads; rows beyond I carry the offset kBig, so their kernel is 0)
-    float cv[2][16], offr[16];
-    const int k0c = col < m ? col : m - 1, k1c = 32 + col < m ? 32 + col : m - 1;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int i = rt * 32 + mfma_row(v, l);
-        offr[v] = tv.off[i];
-        const float* src = a.C + (u * I + (i < I ? i : I - 1)) * (int64_t)m;
-        cv[0][v] = src[k0c];
-        cv[1][v] = src[k1c];
-    }
-    float cb[2][16];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) cb[ct][v] = 0.f;
-
-    const int ne = min(tv.ep[0], kTileEpochs);
-    const float* Ap = tv.A + (size_t)half * IP + rt * 32 + col;   // + slot * 2 IP
-    const float* Bp = tv.B + (size_t)half * 64 + col;             // + slot * 128 (+ 32)
     const bool c0ok = col < m, c1ok = 32 + col < m;
-    for (int e = 0; e < ne; ++e) {
-        const int hi = tv.ep[1 + e];                    // first (largest) t of the stretch
-        const int lo = (e + 1 < ne) ? tv.ep[2 + e] : 0; // first t of the next stretch
-        f32x16 acc0 = {}, acc1 = {};
-        // slots lo .. hi-1 (iterations lo+1 .. hi), and the initial term in stretch 0
-        const int s0 = lo, s1 = hi + (e == 0 ? 1 : 0);
-        int s = s0;
-        for (; s + 4 <= s1; s += 4) {
-            float av[4], bv0[4], bv1[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int sl = (s + q == hi && e == 0) ? T : s + q;
-                av[q] = Ap[(size_t)sl * 2 * IP];
-                bv0[q] = Bp[(size_t)sl * 128];
-                bv1[q] = Bp[(size_t)sl * 128 + 32];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                bv0[q] = c0ok ? bv0[q] : 0.f;
-                bv1[q] = c1ok ? bv1[q] : 0.f;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv0[q], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv1[q], acc1, 0, 0, 0);
-            }
-        }
-        for (; s < s1; ++s) {
-            const int sl = (s == hi && e == 0) ? T : s;
-            const float av = Ap[(size_t)sl * 2 * IP];
-            float bv0 = Bp[(size_t)sl * 128], bv1 = Bp[(size_t)sl * 128 + 32];
-            bv0 = c0ok ? bv0 : 0.f;
-            bv1 = c1ok ? bv1 : 0.f;
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv1, acc1, 0, 0, 0);
-        }
-        // times the stretch's reference kernel Kt = 2^(c c2 - off + rho + phi)
-        float rk0 = tv.rho[e * 64 + col], rk1 = tv.rho[e * 64 + 32 + col];
-        rk0 = c0ok ? rk0 : kNeg;
-        rk1 = c1ok ? rk1 : kNeg;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = rt * 32 + mfma_row(v, l);
-            const float ph = tv.phi[e * IP + i];
-            const float k0 = ex2((fmaf(cv[0][v], a.c2, -offr[v]) + rk0) + ph);
-            const float k1 = ex2((fmaf(cv[1][v], a.c2, -offr[v]) + rk1) + ph);
-            cb[0][v] = fmaf(k0, acc0[v], cb[0][v]);
-            cb[1][v] = fmaf(k1, acc1[v], cb[1][v]);
-        }
-    }
-
-    // gF dF/dC, or the ascent step on C (Adam's bias corrections from the step count)
+    const float* Ap = tv.A + (size_t)half * IP + rt0 * 32 + col;   // + slot * 2 IP (+ 32)
+    const float* Bp = tv.B + (size_t)half * 64 + col;              // + slot * 128 (+ 32)
+    const int ne = min(tv.ep[0], kTileEpochs);
     float bc1 = 1.f, bc2 = 1.f;
     if (a.Cw && a.rule == 0) {
         const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
         bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
         bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
     }
+
+    for (int e = 0; e < ne; ++e) {
+        const int hi = tv.ep[1 + e];                    // first (largest) t of the stretch
+        const int lo = (e + 1 < ne) ? tv.ep[2 + e] : 0; // first t of the next stretch
+        // slots lo .. hi-1 (iterations lo+1 .. hi), then the initial term in stretch 0
+        const int n = hi - lo + (e == 0 ? 1 : 0);
+        auto slot = [&](int q) { return (q >= n || (e == 0 && q == n - 1)) ? T : lo + q; };
+        f32x16 acc[2][2] = {};
+        // two operand buffers, alternating: one group's loads are in flight
+        // while the other group's MFMAs run (slots past n have A = 0)
+        Opd p0[kPre], p1[kPre];
+        auto load_group = [&](Opd (&buf)[kPre], int g) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int i = rt * 32 + mfma_row(v, l);
-        if (i >= I) continue;
+            for (int q = 0; q < kPre; ++q) buf[q] = load_opd<IP>(Ap, Bp, slot(g + q));
+        };
+        auto mfma_group = [&](const Opd (&buf)[kPre], int g) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const int k = ct * 32 + col;
-            if (k >= m) continue;
-            const int64_t idx = (u * I + i) * (int64_t)m + k;
-            const float g = cb[ct][v];
-            if (a.dC) a.dC[idx] = g;
-            if (a.Cw) {
-                const float craw = cv[ct][v];
-                if (a.rule == 0) {
-                    const float gl = -g;
-                    const float mo = a.b1 * a.mom[idx] + (1.f - a.b1) * gl;
-                    const float ve = a.b2 * a.vel[idx] + (1.f - a.b2) * gl * gl;
-                    a.mom[idx] = mo;
-                    a.vel[idx] = ve;
-                    a.Cw[idx] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
-                } else {
-                    a.Cw[idx] = craw + a.lr * g;
+            for (int q = 0; q < kPre; ++q) {
+                const bool ok = g + q < n;
+                const float a0 = ok ? buf[q].a0 : 0.f, a1 = ok ? buf[q].a1 : 0.f;
+                const float b0 = c0ok ? buf[q].b0 : 0.f, b1 = c1ok ? buf[q].b1 : 0.f;
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        };
+        load_group(p0, 0);
+        for (int g = 0; g < n; g += 2 * kPre) {
+            load_group(p1, g + kPre);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_group(p0, g);
+            __builtin_amdgcn_sched_barrier(0);
+            load_group(p0, g + 2 * kPre);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_group(p1, g + kPre);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // times the stretch's reference kernel Kt = 2^(c c2 - off + rho + phi);
+        // the last stretch applies gF dF/dC or the ascent step (Adam's bias
+        // corrections from the step count), earlier ones add into tv.cb
+        const bool last = e + 1 == ne;
+        const float* Cg = opaque_p(a.C);
+        float* cbg = opaque_p(tv.cb);
+        const float* phg = opaque_p(tv.phi) + e * IP;
+        const float* offg = opaque_p(tv.off);
+        const int rte = opaque_s(rt0), Ie = opaque_s(I), me = opaque_s(m);
+        const int64_t ue = (int64_t)opaque_s((int)u);
+        float rk[2] = {tv.rho[e * 64 + col], tv.rho[e * 64 + 32 + col]};
+        rk[0] = c0ok ? rk[0] : kNeg;
+        rk[1] = c1ok ? rk[1] : kNeg;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = (rte + r) * 32 + mfma_row(v, l);
+                const int ic = i < Ie ? i : Ie - 1;
+                const float base = phg[i] - offg[i];
+                float* cbp = cbg + (size_t)i * 64;
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    const int k = ct * 32 + col;
+                    const bool ok = (ct == 0) ? c0ok : c1ok;
+                    const int64_t idx = (ue * Ie + ic) * (int64_t)me + (ok ? k : me - 1);
+                    const float craw = Cg[idx];
+                    float g = ex2(fmaf(craw, a.c2, base) + rk[ct]) * acc[r][ct][v];
+                    if (e > 0) g += cbp[k];
+                    if (!last) {
+                        cbp[k] = g;
+                        continue;
+                    }
+                    if (i >= Ie || !ok) continue;
+                    if (a.dC) opaque_p(a.dC)[idx] = g;
+                    if (a.Cw) {
+                        if (a.rule == 0) {
+                            float* mg = opaque_p(a.mom);
+                            float* vg = opaque_p(a.vel);
+                            const float gl = -g;
+                            const float mo = a.b1 * mg[idx] + (1.f - a.b1) * gl;
+                            const float ve = a.b2 * vg[idx] + (1.f - a.b2) * gl * gl;
+                            mg[idx] = mo;
+                            vg[idx] = ve;
+                            opaque_p(a.Cw)[idx] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
+                        } else {
+                            opaque_p(a.Cw)[idx] = craw + a.lr * g;
+                        }
+                    }
                 }
+                // one row of cells at a time: keeps the scheduler from hoisting
+                // every cell's loads at once
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -832,7 +866,7 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
         const int nb = (int)((a.U - u0) < tb.batch ? (a.U - u0) : tb.batch);
         hipLaunchKernelGGL((k_tbwd<CT, RT, W>), dim3(nb), dim3(64 * W),
                            tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
-        hipLaunchKernelGGL((k_tgrad<IP>), dim3(nb, (a.I + 127) / 128), dim3(256), 0, s, a, tb, u0,
+        hipLaunchKernelGGL((k_tgrad<IP>), dim3(nb, (a.I + 255) / 256), dim3(256), 0, s, a, tb, u0,
                            nb);
     }
 }
@@ -866,6 +900,8 @@ size_t tile_consumer_bytes(const TileEntry* e, int T) {
     o += sizeof(float) * (size_t)kTileEpochs * IP;
     o += sizeof(float) * IP;
     o += sizeof(int) * (size_t)(kTileEpochs + 1);
+    o = (o + 255) / 256 * 256;
+    o += sizeof(float) * IP * 64;
     return (o + 255) / 256 * 256;
 }
 
