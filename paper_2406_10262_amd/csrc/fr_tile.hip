@@ -201,10 +201,19 @@ __device__ __forceinline__ void spread_cols(float* vb, int rslot, bool has, cons
         for (int v = 0; v < NV; ++v) vb[v * 64 + rslot] = val[v];
     }
     lds_wave_fence();
+    // 16-byte reads of the group's 16 slots (64-byte aligned), CT of them used
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < NV; ++v) {
+        const float4* src = (const float4*)(vb + v * 64 + cg * 16);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) out[v][c] = vb[v * 64 + cg * 16 + c];
+        for (int q = 0; q < (CT + 3) / 4; ++q) {
+            const float4 x = src[q];
+            if (4 * q + 0 < CT) out[v][4 * q + 0] = x.x;
+            if (4 * q + 1 < CT) out[v][4 * q + 1] = x.y;
+            if (4 * q + 2 < CT) out[v][4 * q + 2] = x.z;
+            if (4 * q + 3 < CT) out[v][4 * q + 3] = x.w;
+        }
+    }
     lds_wave_fence();
 }
 
@@ -725,15 +734,26 @@ __device__ __forceinline__ Opd load_opd(const float* Ap, const float* Bp, int sl
 // loaded kPre slots ahead of the MFMAs that use them.
 constexpr int kPre = 6;
 
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// The linear block id is mapped so that the NRB row blocks of one consumer
+// share an XCD and are dispatched close together: id = (b / 8) * 8 NRB +
+// rb * 8 + b % 8, so that the consumer's column factors, costs and Adam
+// moments are read from HBM once and then hit that XCD's L2.
+constexpr int kXcds = 8;
+
 template <int IP>
 __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
     if (a.stop && *a.stop) return;   // the outer loop has ended
-    const int b = blockIdx.x;
+    constexpr int NRB = (IP + 255) / 256;   // row blocks per consumer (grid: 8 NRB blocks per 8 consumers)
+    const int id = blockIdx.x;
+    const int grp = id / (kXcds * NRB), rem = id - grp * (kXcds * NRB);
+    const int rb = rem / kXcds;
+    const int b = grp * kXcds + (rem - rb * kXcds);
     if (b >= nb) return;
     const int64_t u = u0 + b;
     const int l = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform in the wave
-    const int rt0 = (blockIdx.y * 4 + wv) * 2;
+    const int rt0 = (rb * 4 + wv) * 2;
     const int I = a.I, m = a.m, T = a.T;
     if (rt0 * 32 >= I) return;
     const TileView tv = tile_view(tb, b, T, IP);
@@ -866,7 +886,9 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
         const int nb = (int)((a.U - u0) < tb.batch ? (a.U - u0) : tb.batch);
         hipLaunchKernelGGL((k_tbwd<CT, RT, W>), dim3(nb), dim3(64 * W),
                            tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
-        hipLaunchKernelGGL((k_tgrad<IP>), dim3(nb, (a.I + 255) / 256), dim3(256), 0, s, a, tb, u0,
+        constexpr int NRB = (IP + 255) / 256;
+        const int groups = (nb + kXcds - 1) / kXcds;
+        hipLaunchKernelGGL((k_tgrad<IP>), dim3(groups * kXcds * NRB), dim3(256), 0, s, a, tb, u0,
                            nb);
     }
 }
