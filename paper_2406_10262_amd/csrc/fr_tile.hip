@@ -732,17 +732,28 @@ __device__ __forceinline__ Opd load_opd(const float* Ap, const float* Bp, int sl
 // 2 (4 rb + v) + 1 (64 rows) of consumer u0 + b and both 32-column tiles, so
 // each slot costs 4 MFMAs for 2 row and 2 column operand loads.  Operands are
 // loaded kPre slots ahead of the MFMAs that use them.
+//
+// The epilogue needs the costs of the wave's 64 rows (the reference kernel
+// Kt = 2^(c c2 - off + rho + phi) is rebuilt from them): they are copied into
+// LDS by direct global-to-LDS loads issued at the start, which complete while
+// the MFMAs run and occupy no registers.  The kernel writes dF/dC: into dC
+// when it is asked for, else into the batch's gradient buffer, from which
+// k_tupd applies the update.
 constexpr int kPre = 6;
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // The linear block id is mapped so that the NRB row blocks of one consumer
 // share an XCD and are dispatched close together: id = (b / 8) * 8 NRB +
-// rb * 8 + b % 8, so that the consumer's column factors, costs and Adam
-// moments are read from HBM once and then hit that XCD's L2.
+// rb * 8 + b % 8, so that the consumer's column factors are read from HBM
+// once and then hit that XCD's L2.
 constexpr int kXcds = 8;
+
+typedef float __attribute__((address_space(1))) gfloat;
+typedef float __attribute__((address_space(3))) lfloat;
 
 template <int IP>
 __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+    extern __shared__ float smem[];
     if (a.stop && *a.stop) return;   // the outer loop has ended
     constexpr int NRB = (IP + 255) / 256;   // row blocks per consumer (grid: 8 NRB blocks per 8 consumers)
     const int id = blockIdx.x;
@@ -760,15 +771,26 @@ __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0
     const int col = l & 31;
     const int half = l >> 5;
     const bool c0ok = col < m, c1ok = 32 + col < m;
+
+    // this wave's LDS: the costs of its rows (row-major, m per row), then the
+    // row term phi - off of the current stretch
+    float* cl = smem + wv * (64 * m + 64);
+    float* bl = cl + 64 * m;
+    {
+        const int r0 = rt0 * 32;
+        const int nrow = min(64, I - r0);
+        const int len = nrow * m;   // floats, in [m, 64 m]
+        const float* src = a.C + (u * I + r0) * (int64_t)m;
+        for (int o = 0; o < len; o += 64) {
+            if (o + l < len)
+                __builtin_amdgcn_global_load_lds((const gfloat*)(src + o + l), (lfloat*)(cl + o), 4,
+                                                 0, 0);
+        }
+    }
     const float* Ap = tv.A + (size_t)half * IP + rt0 * 32 + col;   // + slot * 2 IP (+ 32)
     const float* Bp = tv.B + (size_t)half * 64 + col;              // + slot * 128 (+ 32)
     const int ne = min(tv.ep[0], kTileEpochs);
-    float bc1 = 1.f, bc2 = 1.f;
-    if (a.Cw && a.rule == 0) {
-        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
-        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
-        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
-    }
+    float* gout = a.dC ? a.dC + u * (int64_t)I * m : tv.cb;   // [I][m]
 
     for (int e = 0; e < ne; ++e) {
         const int hi = tv.ep[1 + e];                    // first (largest) t of the stretch
@@ -807,60 +829,76 @@ __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0
             mfma_group(p1, g + kPre);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // times the stretch's reference kernel Kt = 2^(c c2 - off + rho + phi);
-        // the last stretch applies gF dF/dC or the ascent step (Adam's bias
-        // corrections from the step count), earlier ones add into tv.cb
-        const bool last = e + 1 == ne;
-        const float* Cg = opaque_p(a.C);
-        float* cbg = opaque_p(tv.cb);
-        const float* phg = opaque_p(tv.phi) + e * IP;
-        const float* offg = opaque_p(tv.off);
-        const int rte = opaque_s(rt0), Ie = opaque_s(I), me = opaque_s(m);
-        const int64_t ue = (int64_t)opaque_s((int)u);
+        // the stretch's row term phi - off of the wave's 64 rows
+        bl[l] = tv.phi[e * IP + rt0 * 32 + l] - tv.off[rt0 * 32 + l];
+        __builtin_amdgcn_s_waitcnt(0);   // the cost copy and the row terms are in LDS
+        __builtin_amdgcn_wave_barrier();
         float rk[2] = {tv.rho[e * 64 + col], tv.rho[e * 64 + 32 + col]};
         rk[0] = c0ok ? rk[0] : kNeg;
         rk[1] = c1ok ? rk[1] : kNeg;
+        // dF/dC = sum over stretches of Kt (.) acc: stretches before the last
+        // add into gout, the last writes it
+        const bool first = e == 0, last = e + 1 == ne;
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int i = (rte + r) * 32 + mfma_row(v, l);
-                const int ic = i < Ie ? i : Ie - 1;
-                const float base = phg[i] - offg[i];
-                float* cbp = cbg + (size_t)i * 64;
+                // one row of cells at a time, addresses formed here (opaque
+                // operands keep them from being hoisted and kept live)
+                const int Io = opaque_s(I), mo = opaque_s(m);
+                const int il = r * 32 + mfma_row(v, l);   // row within the wave's 64
+                const int i = rt0 * 32 + il;
+                if (i < Io) {
+                    const float base = bl[il];
+                    float* gp = opaque_p(gout) + (int64_t)i * mo;
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct) {
-                    const int k = ct * 32 + col;
-                    const bool ok = (ct == 0) ? c0ok : c1ok;
-                    const int64_t idx = (ue * Ie + ic) * (int64_t)me + (ok ? k : me - 1);
-                    const float craw = Cg[idx];
-                    float g = ex2(fmaf(craw, a.c2, base) + rk[ct]) * acc[r][ct][v];
-                    if (e > 0) g += cbp[k];
-                    if (!last) {
-                        cbp[k] = g;
-                        continue;
-                    }
-                    if (i >= Ie || !ok) continue;
-                    if (a.dC) opaque_p(a.dC)[idx] = g;
-                    if (a.Cw) {
-                        if (a.rule == 0) {
-                            float* mg = opaque_p(a.mom);
-                            float* vg = opaque_p(a.vel);
-                            const float gl = -g;
-                            const float mo = a.b1 * mg[idx] + (1.f - a.b1) * gl;
-                            const float ve = a.b2 * vg[idx] + (1.f - a.b2) * gl * gl;
-                            mg[idx] = mo;
-                            vg[idx] = ve;
-                            opaque_p(a.Cw)[idx] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
-                        } else {
-                            opaque_p(a.Cw)[idx] = craw + a.lr * g;
+                    for (int ct = 0; ct < 2; ++ct) {
+                        const int k = ct * 32 + col;
+                        if (k < mo) {
+                            float g = ex2(fmaf(cl[il * mo + k], a.c2, base) + rk[ct]) * acc[r][ct][v];
+                            if (!first) g += gp[k];
+                            gp[k] = g;
                         }
                     }
                 }
-                // one row of cells at a time: keeps the scheduler from hoisting
-                // every cell's loads at once
                 __builtin_amdgcn_sched_barrier(0);
             }
+        }
+        (void)last;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Update of a batch from its gradient buffer: Adam (MODE 1, bias corrections
+// from the step count) or plain ascent (MODE 2), elementwise over the cells
+// of consumers u0 .. u0 + nb - 1.
+template <int IP, int MODE>
+__global__ __launch_bounds__(256) void k_tupd(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+    if (a.stop && *a.stop) return;   // the outer loop has ended
+    const int b = blockIdx.y;
+    if (b >= nb) return;
+    const int64_t n = (int64_t)a.I * a.m;
+    const int64_t base = (u0 + b) * n;
+    const float* g = tile_view(tb, b, a.T, IP).cb;   // [I][m]
+    float bc1 = 1.f, bc2 = 1.f;
+    if (MODE == 1) {
+        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
+        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
+        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
+    }
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const float gr = g[c];
+        const float craw = a.Cw[base + c];
+        if (MODE == 1) {
+            const float gl = -gr;
+            const float mo = a.b1 * a.mom[base + c] + (1.f - a.b1) * gl;
+            const float ve = a.b2 * a.vel[base + c] + (1.f - a.b2) * gl * gl;
+            a.mom[base + c] = mo;
+            a.vel[base + c] = ve;
+            a.Cw[base + c] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
+        } else {
+            a.Cw[base + c] = craw + a.lr * gr;
         }
     }
 }
@@ -888,8 +926,18 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
                            tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
         constexpr int NRB = (IP + 255) / 256;
         const int groups = (nb + kXcds - 1) / kXcds;
-        hipLaunchKernelGGL((k_tgrad<IP>), dim3(groups * kXcds * NRB), dim3(256), 0, s, a, tb, u0,
-                           nb);
+        if (!a.dC && !a.Cw) continue;
+        // dF/dC into dC when asked for, else into the gradient buffer and applied
+        hipLaunchKernelGGL((k_tgrad<IP>), dim3(groups * kXcds * NRB), dim3(256),
+                           4 * (64 * a.m + 64) * sizeof(float), s, a, tb, u0, nb);
+        if (!a.dC && a.Cw) {
+            const int64_t cells = (int64_t)a.I * a.m;
+            const dim3 ug((unsigned)std::min<int64_t>((cells + 255) / 256, 64), (unsigned)nb);
+            if (a.rule == 0)
+                hipLaunchKernelGGL((k_tupd<IP, 1>), ug, dim3(256), 0, s, a, tb, u0, nb);
+            else
+                hipLaunchKernelGGL((k_tupd<IP, 2>), ug, dim3(256), 0, s, a, tb, u0, nb);
+        }
     }
 }
 
