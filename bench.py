@@ -79,7 +79,7 @@ def kernel_source_hash():
     (a profile stays valid across comment edits, not across code changes)."""
     import re
     h = hashlib.sha256()
-    for f in ("fr_fused.hip", "fr_device.h"):
+    for f in ("fr_fused.hip", "fr_tile.hip", "fr_device.h"):
         with open(os.path.join(ROOT, "paper_2406_10262_amd", "csrc", f)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
@@ -163,9 +163,14 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
         prof = load_profile(k, cfg_name)
         if prof is not None:
             ent["profile_kernel"] = prof.get("kernel")
-            if "lds_bytes_per_launch" in prof:
-                ent["lds_TBps"] = prof["lds_bytes_per_launch"] / sec / 1e12
-                ent["lds_frac"] = prof["lds_bytes_per_launch"] / sec / LDS_PEAK
+            if "lds_instr_per_launch" in prof:
+                # LDS data rate estimated as 4 bytes per lane per LDS instruction
+                # (the tile kernels' exchanges are mostly 32-bit; 16-byte reads
+                # make this a lower bound)
+                lds_b = prof["lds_instr_per_launch"] * 64 * 4
+                ent["lds_instr_per_s"] = prof["lds_instr_per_launch"] / sec
+                ent["lds_TBps"] = lds_b / sec / 1e12
+                ent["lds_frac"] = lds_b / sec / LDS_PEAK
             if "trans_per_launch" in prof:
                 ent["trans_per_s"] = prof["trans_per_launch"] / sec
                 ent["trans_issued_per_cell_iter"] = prof["trans_per_launch"] / per_launch
@@ -195,8 +200,8 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
                      "vector rate (packed FMA); this build issues single-lane FP32 only "
                      "(frac_nonpacked_fp32 is against that ceiling, 78.6 TFLOP/s)"}
     if dom in kernels:
-        for key in ("lds_TBps", "lds_frac", "trans_per_s", "trans_issued_per_cell_iter",
-                    "valu_issue_frac"):
+        for key in ("lds_TBps", "lds_frac", "lds_instr_per_s", "trans_per_s",
+                    "trans_issued_per_cell_iter", "valu_issue_frac"):
             if key in kernels[dom]:
                 roof[key] = kernels[dom][key]
     print(f"bench: kernels ({form} form) {fk} {ks[fk][0]:.3f} ms {bk} {ks[bk][0]:.3f} ms "
