@@ -14,6 +14,8 @@ One bench step is one pass of the whole hot path over the workload:
   potentials kept every 50 iterations.
 * C4: one batched solve of the 128 uneven instances (persistent kernels, one
   graph per outer step).
+* paper: context rows -- the paper's experiment shapes and the sweep over
+  consumers (one solve of 10 outer steps each, spot parity on 8 consumers).
 
 Inputs are resident in HBM before timing starts.  Prints one JSON line with
 throughput in plan-cells x Sinkhorn-iterations per second, the NSW relative
@@ -774,12 +776,72 @@ def bench_batched(args, fr, lib, dev):
     return out
 
 
+def bench_paper(args, fr, lib, dev):
+    """Context rows: the paper's three experiment shapes and the sweep over
+    consumers at 250 items x 11 columns (Section 4.2 states the GPU time is
+    almost independent of the number of consumers).  Each is one solve of
+    N = 10 outer steps (T = 200) timed after a warm-up solve, with spot parity
+    against the FP64 oracle: the plans of 8 sampled consumers at the GPU's own
+    final costs."""
+    import torch
+    import oracle
+    import workloads as W
+
+    def one(inst, plain):
+        ctx = fr.Context(0)
+        prob = fr.Problem(torch.from_numpy(inst.r).to(dev), torch.from_numpy(inst.e).to(dev),
+                          float(inst.eps), inst.T)
+        lr = float(inst.lr)
+        fr.solve(ctx, prob, 1, lr, want_X=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fr.solve(ctx, prob, inst.N, lr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sel = np.sort(np.random.default_rng(60).choice(inst.U, min(8, inst.U), replace=False))
+        idx = torch.from_numpy(sel).to(dev)
+        Xr = oracle.forward(res["C"][idx].double().cpu().numpy(), float(inst.eps), inst.T)
+        xerr = float(np.max(np.abs(res["X"][idx].double().cpu().numpy() - Xr)))
+        cells = inst.U * inst.I * inst.m
+        rec = {"U": inst.U, "I": inst.I, "m": inst.m, "T": inst.T, "N": inst.N,
+               "seconds": dt, "cell_iters_per_s": cells * inst.T * inst.N / dt,
+               "launch": list(ctx.get_launch(inst.U, inst.I, inst.m)),
+               "spot_X_maxabs_err_8_consumers": xerr}
+        if plain:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fr.solve_plain(ctx, prob, inst.N, lr, want_X=False)
+            torch.cuda.synchronize()
+            rec["plain_seconds"] = time.perf_counter() - t0
+            rec["fused_speedup"] = rec["plain_seconds"] / dt
+        ctx.close()
+        print(f"bench: {inst.name} U={inst.U} I={inst.I} m={inst.m}: {dt * 1e3:.1f} ms, "
+              f"spot X err {xerr:.2e}", flush=True)
+        return rec
+
+    shapes = {name: one(W.paper_shape(name), not args.skip_plain) for name in W.PAPER_SHAPES}
+    sweep = [one(W.user_sweep(U), False) for U in (250, 500, 1000, 2000, 4000, 8000, 16000,
+                                                    32000, 64000)]
+    t_small = sweep[0]["seconds"]
+    for r in sweep:
+        r["time_vs_250_consumers"] = r["seconds"] / t_small
+    config = {"workload": "context rows: the paper's experiment shapes (1000 x 500 x 11, "
+                          "1014 x 100 x 11, 250 x 250 x 11) and 250 to 64000 consumers x 250 "
+                          "items x 11 columns; low-rank-16 sigmoid relevance, eps 0.02, T 200, "
+                          "N 10 Adam steps",
+              "step": "one solve per shape"}
+    last = sweep[-1]
+    out = base_record(args, last["cell_iters_per_s"], last["seconds"] * 1e3, config)
+    out.update({"paper_shapes": shapes, "user_sweep": sweep, "paper_context": PAPER_CONTEXT})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="C5", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "paper"])
     ap.add_argument("--skip-rest", action="store_true",
                     help="C5: stop after the timed steps (no complete 50-step trajectory)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
@@ -826,6 +888,8 @@ def main():
         out = bench_batched(args, fr, lib, dev)
     elif args.workload == "C5":
         out = bench_c5(args, fr, lib, dev)
+    elif args.workload == "paper":
+        out = bench_paper(args, fr, lib, dev)
     else:
         out = bench_solve(args, fr, lib, dev, args.workload)
     if out is not None:

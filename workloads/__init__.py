@@ -29,7 +29,8 @@ import numpy as np
 __all__ = [
     "Instance", "exposure", "relevance_uniform", "relevance_lowrank",
     "config", "CONFIG_NAMES", "batched_shapes", "batched_instance",
-    "random_costs", "subsample_users", "small_instance",
+    "random_costs", "subsample_users", "small_instance", "PAPER_SHAPES", "paper_shape",
+    "user_sweep",
 ]
 
 
@@ -120,6 +121,30 @@ def config(name: str, U: Optional[int] = None) -> Instance:
         r = relevance_lowrank(U_, 1000, 32, 1.0 / 32, rng)
         return Instance("C5", U_, 1000, 50, r, exposure(50), np.float32(0.01), 300, 50, 5)
     raise KeyError(name)
+
+
+# The shapes of the paper's experiments (Section 4: Figs. 1-3), m counting the
+# dummy column (top-10 rankings plus the dummy), with seeds 6-8; the sweep over
+# consumers of Section 4.2 at 250 items (seed 9).  Entropic weight, iteration
+# counts and relevance model as the 2000 x 100 x 10 workload, N = 10 outer steps.
+PAPER_SHAPES = {"fig1": (1000, 500, 11, 6), "fig2": (1014, 100, 11, 7), "fig3": (250, 250, 11, 8)}
+
+
+def paper_shape(name: str, U: Optional[int] = None, N: int = 10) -> Instance:
+    """One of the paper's shapes (PAPER_SHAPES), low-rank-16 sigmoid relevance,
+    eps 0.02, T 200."""
+    U0, I, m, seed = PAPER_SHAPES[name]
+    U_ = U0 if U is None else U
+    rng = np.random.default_rng(seed)
+    r = relevance_lowrank(U_, I, 16, 1.0 / 16, rng)
+    return Instance(name, U_, I, m, r, exposure(m), np.float32(0.02), 200, N, seed)
+
+
+def user_sweep(U: int, N: int = 10) -> Instance:
+    """The consumer sweep: U consumers x 250 items x 11 columns (seed 9)."""
+    rng = np.random.default_rng(9)
+    r = relevance_lowrank(U, 250, 16, 1.0 / 16, rng)
+    return Instance(f"sweep{U}", U, 250, 11, r, exposure(11), np.float32(0.02), 200, N, 9)
 
 
 def batched_shapes(n_inst: int = 128, seed: int = 4):
