@@ -37,14 +37,16 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # MI355X (gfx950): 256 CUs x 4 SIMDs, 2.4 GHz.  The published FP32 vector
-# peak, 157.3 TFLOP/s, counts packed FMAs (two lanes of FMA per lane-slot, an
-# FMA being 2 flops); this build compiles with packed FP32 disabled, so its
-# single-lane FP32 VALU issue tops out at half of it, 78.6 TFLOP/s
-# (39.3 T FMA/s).  The roofline reports both fractions; the headline one is
-# against the published 157.3.
-CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-PEAK_FP32_FLOPS = 157.3e12                         # published, packed FP32
-PEAK_FP32_NONPACKED = CUS * SIMDS * LANES * CLOCK * 2   # 78.6e12 FLOP/s
+# peak is 157.3 TFLOP/s: 32 FMA lanes per clock per SIMD, an FMA being 2
+# flops.  Single-lane FP32 code (this build compiles with packed FP32
+# disabled) reaches it too: measured on the device, four waves per SIMD issue
+# a wave-wide v_fmac_f32 every 2.25 clocks per SIMD (0.445 of 0.5), while one
+# wave issues at most one VALU instruction per ~4.5 clocks, so that two waves
+# per SIMD (the tile kernels' occupancy) bound a kernel at about 0.44 wave
+# instructions per clock.  The roofline is against the published 157.3.
+CUS, SIMDS, CLOCK = 256, 4, 2.4e9
+PEAK_FP32_FLOPS = 157.3e12                         # published FP32 vector
+VALU_LANE_OPS_PEAK = CUS * SIMDS * 32 * CLOCK      # 78.6e12 FP32 lane-ops/s (FMA = 2 flops)
 LDS_PEAK = CUS * 128 * CLOCK                       # 128 B per clock per CU: 78.6 TB/s
 # Algorithmic FP32 flops per cell-iteration (FMA = 2, add or multiply = 1),
 # the minimum the method needs, independent of this implementation:
@@ -57,9 +59,11 @@ LDS_PEAK = CUS * 128 * CLOCK                       # 128 B per clock per CU: 78.
 #     (two FMAs): 10 flops (log domain: plus one exponential).
 # The tile kernels of large plans compute the scaling form (their reverse
 # sweep's cost-adjoint FMAs run as an FP32 matrix-core contraction, whose
-# published dense peak is also 157.3 TFLOP/s).
+# published dense peak is also 157.3 TFLOP/s); their forward keeps the row
+# scalings u_i = 1 / s_i of every iteration, so the sweep needs no row sums s_i:
+# 8 flops per reverse cell-iteration.
 FWD_FLOPS = {"log": 4, "scaling": 4, "tile": 4}
-BWD_FLOPS = {"log": 10, "scaling": 10, "tile": 10}
+BWD_FLOPS = {"log": 10, "scaling": 10, "tile": 8}
 FWD_TRANS = {"log": 1, "scaling": 0, "tile": 0}
 BWD_TRANS = {"log": 1, "scaling": 0, "tile": 0}
 FORMS = {0: "log", 1: "scaling", 2: "tile"}
@@ -160,7 +164,6 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
                "cell_iters_per_s": per_launch / sec, "alg_flops_per_cell_iter": fl,
                "achieved_tflops": per_launch * fl / sec / 1e12,
                "frac_fp32_peak": per_launch * fl / sec / PEAK_FP32_FLOPS,
-               "frac_nonpacked_fp32": per_launch * fl / sec / PEAK_FP32_NONPACKED,
                "alg_transcendentals_per_cell_iter": tr}
         prof = load_profile(k, cfg_name)
         if prof is not None:
@@ -178,7 +181,7 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
                 ent["trans_issued_per_cell_iter"] = prof["trans_per_launch"] / per_launch
             if "valu_lane_ops_per_launch" in prof:
                 ent["valu_issue_frac"] = (prof["valu_lane_ops_per_launch"] / sec
-                                          / (PEAK_FP32_NONPACKED / 2))
+                                          / VALU_LANE_OPS_PEAK)
         kernels[k] = ent
     dom = max(ks, key=lambda k: ks[k][0])
     avg_ms, _, fl, _ = ks[dom]
@@ -188,7 +191,6 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
     roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
             "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
-            "frac_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
             "hbm_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
             "hbm_frac": None if traffic is None else traffic / (avg_ms * 1e-3) / HBM_PEAK,
             "alg_hbm_bytes_per_launch": alg_bytes(dom, prob),
@@ -199,8 +201,9 @@ def kernel_roofline(fr, lib, ctx, prob, N, lr, cfg_name, form="scaling", C0=None
             "model": f"{fl} algorithmic FP32 flops (FMA = 2) per cell-iteration of the "
                      f"{dom} arithmetic, U*I*m*T cell-iterations per launch, mean launch time "
                      "from HIP events on the solve's stream; peak = the published MI355X FP32 "
-                     "vector rate (packed FMA); this build issues single-lane FP32 only "
-                     "(frac_nonpacked_fp32 is against that ceiling, 78.6 TFLOP/s)"}
+                     "vector rate (32 FMA lanes per clock per SIMD), which single-lane FP32 "
+                     "code also reaches at four waves per SIMD; valu_issue_frac = VALU lane "
+                     "operations per second (profiler counts) over 78.6e12"}
     if dom in kernels:
         for key in ("lds_TBps", "lds_frac", "lds_instr_per_s", "trans_per_s",
                     "trans_issued_per_cell_iter", "valu_issue_frac"):

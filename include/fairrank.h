@@ -253,7 +253,9 @@ fr_status fr_grad_converged(fr_ctx* ctx, const fr_problem* prob, const float* C,
  * dC = gF * dF/dC [U][I][m] and, if dr is not NULL, dr = gF * dF/dr [U][I].
  * The forward is recomputed from C; potentials are kept every
  * checkpoint_every iterations (>= 1) and the segments between them are
- * recomputed during the reverse sweep. */
+ * recomputed during the reverse sweep.  Asynchronous: conditions found on the
+ * device (a tile plan whose sweep needs more than 16 reference kernels,
+ * FR_E_UNSUPPORTED) are reported by fr_sync_status on the same workspace. */
 fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const double* imp,
                       double gF, float* dC, float* dr, int32_t checkpoint_every,
                       void* ws, size_t ws_bytes, void* stream);

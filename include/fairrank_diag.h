@@ -44,6 +44,20 @@ fr_status fr_ctx_kernel_forms(fr_ctx* ctx, int64_t n_users, int32_t n_items, int
 fr_status fr_ctx_bwd_lds_rows(fr_ctx* ctx, int64_t n_users, int32_t n_items, int32_t m,
                               int32_t checkpoint_every, int32_t* rows);
 
+/* Row store of the tile kernels (plans of 40..50 columns and 513..1024
+ * items, every iterate kept): while enabled (the default), the forward that
+ * precedes a reverse sweep keeps each consumer's row scaling of every
+ * iteration and the reference kernel of each stretch between rebases in the
+ * workspace, and the sweep works in those stretches and takes the row
+ * scalings from there instead of forming the row sums again (one multiply-add
+ * per plan cell and iteration fewer).  The workspace (fr_workspace_bytes)
+ * reserves T * 1024 + 16 * 1088 floats per consumer for it, for all consumers
+ * or, beyond 144 GiB, for whole batches of 6144 consumers; the others are
+ * swept without it.  A forward that had more than 16 stretches makes the
+ * sweep report FR_E_UNSUPPORTED.  enable = 0 sweeps every consumer without
+ * the store (its own rebases; the same limit of 16 applies to them). */
+fr_status fr_ctx_set_row_store(fr_ctx* ctx, int enable);
+
 /* ALU microbenchmark on the current device, default stream, synchronous:
  * kind 0 = dependent chains of v_exp_f32, 1 = chains of FP32 FMA, 2 = one
  * exponential followed by five FMAs.  `blocks` blocks of 256 threads, each

@@ -96,6 +96,7 @@ def load():
     lib.fr_workspace_init.argtypes = [P, P, SZ, P]
     lib.fr_set_launch.argtypes = [P, I32, I32, I32, I32]
     lib.fr_ctx_set_form.argtypes = [P, I32, I32]
+    lib.fr_ctx_set_row_store.argtypes = [P, ctypes.c_int]
     lib.fr_rank_maxrele.argtypes = [P, PP, P, P, I32, P]
     lib.fr_rank_greedy.argtypes = [P, PP, P, P, I32, P, P]
     lib.fr_get_launch.argtypes = [P, I64, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -110,7 +111,7 @@ def load():
                  "fr_workspace_bytes_batched", "fr_solve_batched", "fr_autotune",
                  "fr_set_launch", "fr_get_launch", "fr_workspace_bytes_metrics", "fr_metrics",
                  "fr_solve_progress", "fr_grad_converged", "fr_ctx_set_form",
-                 "fr_rank_maxrele", "fr_rank_greedy"):
+                 "fr_ctx_set_row_store", "fr_rank_maxrele", "fr_rank_greedy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,6 +167,11 @@ class Context:
         default) or "log" (log-domain) for the fixed-T forward of later calls."""
         code = {"log": FR_FORM_LOG, "scaling": FR_FORM_SCALING}[form]
         _check(load().fr_ctx_set_form(self.handle, code, int(absorb_every)), "fr_ctx_set_form")
+
+    def set_row_store(self, enable: bool = True):
+        """fr_ctx_set_row_store: whether the tile forward keeps its row
+        scalings for the reverse sweep (the default) or the sweep forms them."""
+        _check(load().fr_ctx_set_row_store(self.handle, int(bool(enable))), "fr_ctx_set_row_store")
 
     def set_launch(self, n_items: int, m: int, lanes: int, rows: int):
         _check(load().fr_set_launch(self.handle, n_items, m, lanes, rows), "fr_set_launch")
@@ -319,8 +325,9 @@ def metrics(ctx: Context, prob: Problem, X: torch.Tensor, per_item: bool = False
 
 
 def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF: float = 1.0,
-             want_dr: bool = True, K: int = 1):
-    """fr_backward: (gF dF/dC, gF dF/dr) through the T unrolled iterations."""
+             want_dr: bool = True, K: int = 1, sync: bool = True):
+    """fr_backward: (gF dF/dC, gF dF/dr) through the T unrolled iterations;
+    with sync, the device flags are read (fr_sync_status) and raised."""
     U, I, m = prob.U, prob.I, prob.m
     _f32(C, (U, I, m), "C")
     if imp.dtype != torch.float64 or imp.numel() != I or not imp.is_cuda:
@@ -333,6 +340,9 @@ def backward(ctx: Context, prob: Problem, C: torch.Tensor, imp: torch.Tensor, gF
     _check(load().fr_backward(ctx.handle, ctypes.byref(p), _ptr(C), _ptr(imp), float(gF), _ptr(dC),
                               _ptr(dr), int(K), _ptr(ws), ws.numel(), _stream(C.device)),
            "fr_backward")
+    if sync:
+        _check(load().fr_sync_status(ctx.handle, _ptr(ws), _stream(C.device)),
+               "fr_backward (device)")
     return dC, dr
 
 

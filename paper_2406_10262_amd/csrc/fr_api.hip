@@ -35,6 +35,7 @@ struct fr_ctx {
     double fwd_ms = 0.0, bwd_ms = 0.0;
     int64_t fwd_n = 0, bwd_n = 0;
     size_t max_lds = 64 * 1024;                           // LDS a block may use on the device
+    bool row_store = true;     // tile plans: the forward keeps its row scalings for the sweep
     void* scratch = nullptr;   // device address of this device's fr_step_noalloc array
 };
 
@@ -292,6 +293,9 @@ struct Layout {
     int nchunk, nck, hs;
     size_t tile_stride;    // bytes per consumer of the tile reverse sweep's buffer (0: none)
     int64_t tile_batch;    // consumers per batch
+    size_t rows;           // the tile forward's row scalings for the sweep
+    size_t rows_stride;    // bytes per consumer (0: none)
+    int64_t rows_n;        // consumers kept: all, or whole batches within kRowStoreCap
 };
 
 int n_checkpoints(int T, int K) { return (T + K - 1) / K + 1; }
@@ -336,13 +340,20 @@ Layout layout(const fr_problem* p, int K, bool tol = false, bool conv = false) {
     L.tile = off;
     L.tile_stride = 0;
     L.tile_batch = 0;
+    L.rows_stride = 0;
+    L.rows_n = 0;
     if (K <= 1 && !conv) {
         if (const TileEntry* te = tile_entry(p->m, I)) {
             L.tile_stride = tile_consumer_bytes(te, p->sinkhorn_iters);
             L.tile_batch = std::min<int64_t>(U, kTileBatch);
             off += align_up(L.tile_stride * (size_t)L.tile_batch);
+            L.rows_stride = tile_row_bytes(te, p->sinkhorn_iters);
+            const int64_t fit = (int64_t)(kRowStoreCap / L.rows_stride);
+            L.rows_n = U <= fit ? U : fit / L.tile_batch * L.tile_batch;
         }
     }
+    L.rows = off;
+    off += align_up(L.rows_stride * (size_t)L.rows_n);
     L.total = off;
     return L;
 }
@@ -450,12 +461,18 @@ BwdArgs bwd_args(const fr_problem* p, const Shape& sh, const float* C) {
     return a;
 }
 
-// The tile reverse sweep's buffer and the flag word, from the workspace.
-void attach_tile(BwdArgs& b, const Layout& Lw, char* w) {
+// The tile reverse sweep's buffer and the flag word, from the workspace, and
+// the row store that the forward a fills and the sweep b reads (unless the
+// context keeps no row scalings).
+void attach_tile(FwdArgs& a, BwdArgs& b, const Layout& Lw, char* w, const fr_ctx* ctx) {
     b.tile.base = w + Lw.tile;
     b.tile.stride = Lw.tile_stride;
     b.tile.batch = Lw.tile_batch;
     b.flags = &((WsHeader*)(w + Lw.hdr))->flags;
+    RowStore rs{};
+    if (ctx->row_store && Lw.rows_n > 0) rs = {w + Lw.rows, Lw.rows_stride, Lw.rows_n};
+    a.rows = rs;
+    b.rows = rs;
 }
 
 fr_status launch_fwd(const Shape& sh, const FwdArgs& a, hipStream_t s) {
@@ -963,7 +980,6 @@ fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const
     a.hist = (float*)(w + Lw.hist);
     a.K = K;
     a.nck = Lw.nck;
-    if ((st = launch_fwd(sh, a, s))) return st;
     BwdArgs b = bwd_args(prob, sh, C);
     b.hist = a.hist;
     b.K = K;
@@ -972,7 +988,8 @@ fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const
     b.gF = gF;
     b.dC = dC;
     b.dr = dr;
-    attach_tile(b, Lw, w);
+    attach_tile(a, b, Lw, w, ctx);
+    if ((st = launch_fwd(sh, a, s))) return st;
     return launch_bwd(sh, b, s);
 }
 
@@ -1016,7 +1033,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     b.K = K;
     b.nck = Lw.nck;
     b.imp = imp;
-    attach_tile(b, Lw, w);
+    attach_tile(a, b, Lw, w, ctx);
     b.Cw = C;
     b.mom = adam_m;
     b.vel = adam_v;
@@ -1111,6 +1128,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     // final forward: X(C_N) and F_N (also after a stop)
     a.hist = nullptr;
     a.stop = nullptr;
+    a.rows = RowStore{};
     a.X = X_out;
     a.x_bf16 = (x_dtype == FR_BF16);
     if (conv) {
@@ -1220,6 +1238,12 @@ fr_status fr_ctx_set_form(fr_ctx* ctx, int32_t form, int32_t absorb_every) {
     if ((form != FR_FORM_LOG && form != FR_FORM_SCALING) || absorb_every < 0) return FR_E_PARAM;
     ctx->form = form;
     ctx->absorb = absorb_every;
+    return FR_OK;
+}
+
+fr_status fr_ctx_set_row_store(fr_ctx* ctx, int enable) {
+    if (!ctx) return FR_E_NULL;
+    ctx->row_store = enable != 0;
     return FR_OK;
 }
 
@@ -1609,7 +1633,7 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             b.nck = Lw.nck;
             double* impw = (double*)(w + Lw.imp);
             b.imp = impw;
-            attach_tile(b, Lw, w);
+            attach_tile(a, b, Lw, w, ctx);
             if (sh.tile_bwd && Lw.tile_stride == 0) continue;
             // one warm-up repetition, then the fastest of three
             float tot = 1e30f;

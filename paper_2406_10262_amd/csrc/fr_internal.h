@@ -24,6 +24,15 @@ struct WsHeader {
 // ---------------------------------------------------------------------------
 // Fused forward: one team of L lanes per consumer, R plan rows per lane held
 // in registers, MP (>= m) columns per row.
+// Row scalings of the tile forward (fr_tile.hip), kept for its reverse sweep:
+// per consumer u < n, the row scaling of every iteration and the reference
+// kernel of every stretch between rebases.
+struct RowStore {
+    char* base;        // n consumers x stride bytes (or null: not kept)
+    size_t stride;     // bytes per consumer
+    int64_t n;         // consumers 0 .. n-1 are kept
+};
+
 struct FwdArgs {
     const float* C;        // [U][I][m]
     const float* r;        // [U][I]
@@ -38,6 +47,7 @@ struct FwdArgs {
     int64_t* iters;        // sum of the iterations used, added per consumer (or null)
     float tol;             // > 0: stop a consumer once no potential moves by more than tol
     int absorb;            // scaling form: also absorb every `absorb` iterations (0: on range only)
+    RowStore rows;         // tile forward: row scalings for the reverse sweep (or base null)
     int64_t U;
     int I, m, T, K, nck, hs, L, x_bf16;
     float c2;              // -1 / (eps ln 2): exponent scale of a cost
@@ -74,6 +84,7 @@ struct BwdArgs {
     float cg_tol;             // implicit form: relative residual to stop at
     int64_t step_const;
     TileBuf tile;             // tile reverse sweep: factor buffer (fr_tile.hip)
+    RowStore rows;            // tile reverse sweep: the forward's row scalings (or base null)
     uint32_t* flags;          // device flag word (FLAG_EPOCHS), or null
     double gF;
     int64_t U;
@@ -138,6 +149,10 @@ struct TileEntry {
 };
 const TileEntry* tile_entry(int m, int I);
 size_t tile_consumer_bytes(const TileEntry* e, int T);
+size_t tile_row_bytes(const TileEntry* e, int T);
+// Most bytes of row scalings the workspace keeps (consumers beyond are swept
+// without them, in whole batches).
+constexpr size_t kRowStoreCap = (size_t)144 << 30;
 // Consumers per batch of the tile reverse sweep.
 constexpr int64_t kTileBatch = 6144;
 

@@ -141,6 +141,7 @@ struct TLane {
     bool writer;                // holds the wave's column sums (q == 0)
     int rcol;                   // column this lane reduces across waves (or -1)
     int rslot;                  // its slot in the column group (cg * 16 + slot)
+    int pslot;                  // where its wave sum sits in a wave's partials (cg * 16 + 4 rho + q)
     __device__ __forceinline__ TLane() {
         const int tid = threadIdx.x;
         l = tid & 63;
@@ -152,6 +153,7 @@ struct TLane {
         writer = q == 0;
         rcol = -1;
         rslot = 0;
+        pslot = cg * 16 + rho * 4 + q;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -163,29 +165,35 @@ struct TLane {
     }
 };
 
-// Writers put the wave's column sums in part[w][slot] (64 slots per wave, so
-// that the lanes of one access touch consecutive words: no bank conflicts).
+// Each writer (lane 16 rho + cg) stores its row's four sums z[0..3] with one
+// 16-byte write at part[w][cg][rho][0..3]: the 16 writers of a wave fill its 64
+// words (every slot written, unused ones with finite filler sums).
 template <int CT, int W>
 __device__ __forceinline__ void put_partials(const TLane<CT, W>& t, const float (&z)[Slots<CT>::H2],
                                              float* part) {
+    constexpr int H2 = Slots<CT>::H2;
+    static_assert(H2 <= 4, "four column slots per 16-lane row");
     if (!t.writer) return;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        if (r != t.rho) continue;
-#pragma unroll
-        for (int qq = 0; qq < Slots<CT>::H2; ++qq)
-            if (Slots<CT>::ok(r, qq)) part[t.w * 64 + t.cg * 16 + Slots<CT>::slot(r, qq)] = z[qq];
-    }
+    float4 v;
+    v.x = z[0];
+    v.y = H2 > 1 ? z[H2 > 1 ? 1 : 0] : 0.f;
+    v.z = H2 > 2 ? z[H2 > 2 ? 2 : 0] : 0.f;
+    v.w = H2 > 3 ? z[H2 > 3 ? 3 : 0] : 0.f;
+    *(float4*)(part + t.w * 64 + t.cg * 16 + t.rho * 4) = v;
 }
 
 // Team total of the lane's reduced column, summed in wave order (identical in
-// every wave).  Call after the barrier that follows put_partials.
+// every wave); lanes that reduce no column get a finite value they must not
+// use.  The W reads are issued together.  Call after the barrier that follows
+// put_partials.
 template <int CT, int W>
 __device__ __forceinline__ float team_total(const TLane<CT, W>& t, const float* part) {
-    if (t.rcol < 0) return 0.f;
+    float x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = part[w * 64 + t.pslot];
     float s = 0.f;
 #pragma unroll
-    for (int w = 0; w < W; ++w) s += part[w * 64 + t.rslot];
+    for (int w = 0; w < W; ++w) s += x[w];
     return s;
 }
 
@@ -311,6 +319,31 @@ __device__ __forceinline__ void tile_rebuild(const float* C, int64_t u, int I, i
         for (int c = 0; c < CT; ++c) kt[j][c] = ex2((fmaf(kt[j][c], c2, -off[j]) + gam[c]) + ph[j]);
 }
 
+// Per-consumer area of the row store (RowStore in fr_internal.h), written by
+// the forward for its reverse sweep.  Rows are kept in lane order, row group
+// major ([rg][j], row i = j RG + rg), so that a lane's RT rows are contiguous.
+struct RowView {
+    float* us;    // [T][RG][RT]  row scaling u_i of iteration t = 1..T
+    float* ph;    // [kTileEpochs][RG][RT]  row offsets of each stretch's kernel
+    float* gam;   // [kTileEpochs][64]  column potentials of each stretch's kernel
+    int* sep;     // [kTileEpochs + 1]: sep[0] = number of stretches (uncapped),
+                  // sep[1 + e] = first iteration of stretch e
+};
+
+__device__ __forceinline__ RowView row_view(const RowStore& rs, int64_t u, int T, int IP) {
+    char* base = rs.base + u * rs.stride;
+    RowView v;
+    size_t o = 0;
+    v.us = (float*)(base + o);
+    o += sizeof(float) * (size_t)T * IP;
+    v.ph = (float*)(base + o);
+    o += sizeof(float) * (size_t)kTileEpochs * IP;
+    v.gam = (float*)(base + o);
+    o += sizeof(float) * (size_t)kTileEpochs * 64;
+    v.sep = (int*)(base + o);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 template <int CT, int RT, int W>
 __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
@@ -325,10 +358,6 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 
     float kt[RT][CT], off[RT], om[RT];
     tile_load<CT, RT, W>(a.C, u, I, m, a.c2, t, kt, off, om);
-#pragma unroll
-    for (int j = 0; j < RT; ++j)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) kt[j][c] = ex2(kt[j][c]);   // gam = 0, ph = 0
 
     // the reducing lane's column: b, scaling, absorbed potential
     const bool live = t.rcol >= 0 && t.rcol < m;
@@ -350,6 +379,37 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
         ph[j] = 0.f;
         us[j] = 1.f;
     }
+    // the first kernel by the same formula as every rebuild (the reverse
+    // sweep rebuilds it bit for bit from the stored references)
+    tile_rebuild<CT, RT, W>(a.C, u, I, m, a.c2, t, off, gam, ph, kt);
+    // Rows beyond I have Kt = 0 exactly: their row sums start from kTiny, so
+    // that u stays finite and Kt u = 0 without a per-row condition (the
+    // added kTiny is below half an ulp of any row sum of a real row).
+
+    // row store: the row scaling of every iteration and the references of
+    // every stretch (stretch 0: gam = 0 on live columns, ph = 0)
+    const bool store = a.rows.base && u < a.rows.n;
+    RowView rv{};
+    int nst = 0;
+    auto put_stretch = [&](int first_it) __attribute__((always_inline)) {
+        if (nst < kTileEpochs) {
+            if (t.w == 0 && t.rcol >= 0) rv.gam[nst * 64 + t.rcol] = gd;
+            if (t.cg == 0) {
+                float4* dst = (float4*)(rv.ph + ((size_t)nst * RG + t.rg) * RT);
+#pragma unroll
+                for (int q = 0; q < RT / 4; ++q)
+                    dst[q] = make_float4(ph[4 * q], ph[4 * q + 1], ph[4 * q + 2], ph[4 * q + 3]);
+            }
+            if (threadIdx.x == 0) rv.sep[1 + nst] = first_it;
+        }
+        ++nst;
+    };
+    static_assert(RT == 8, "two rows per lane of a quad in the row store");
+    const bool cg0 = t.cg == 0, cg1 = t.cg == 1, cg2 = t.cg == 2;
+    if (store) {
+        rv = row_view(a.rows, u, a.T, RT * RG);
+        put_stretch(1);
+    }
     float* hist = a.hist ? a.hist + u * (int64_t)a.nck * a.hs : nullptr;
     auto put_hist = [&](float* dst) {
         if (t.w == 0 && t.rcol >= 0 && t.rcol < a.hs) dst[t.rcol] = fmaxf(gd + lg2(vd), kNeg);
@@ -357,24 +417,36 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
     if (hist) put_hist(hist);
 
     for (int it = 1; it <= a.T; ++it) {
-        // row half-step: u_i = 1 / sum_k Kt_ik v_k
-        float wj[RT];
+        // row half-step: u_i = 1 / sum_k Kt_ik v_k (the RT sums interleaved)
+        {
+            float sr[RT];
 #pragma unroll
-        for (int j = 0; j < RT; ++j) {
-            float ps[2] = {0.f, 0.f};
+            for (int j = 0; j < RT; ++j) sr[j] = kTiny;
 #pragma unroll
-            for (int c = 0; c < CT; ++c) ps[c & 1] = fmaf(kt[j][c], v[c], ps[c & 1]);
-            const float s = quad_sum(ps[0] + ps[1]);
-            us[j] = (om[j] > 0.f) ? rcp(s) : 0.f;
-            wj[j] = us[j];
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int j = 0; j < RT; ++j) sr[j] = fmaf(kt[j][c], v[c], sr[j]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < RT; ++j) sr[j] += dpp_mov<kQuadXor1>(sr[j]);
+#pragma unroll
+            for (int j = 0; j < RT; ++j) sr[j] += dpp_mov<kQuadXor2>(sr[j]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < RT; ++j) us[j] = rcp(sr[j]);
+        }
+        if (store) {   // lane cg of the quad keeps rows 2 cg, 2 cg + 1
+            const float x0 = cg0 ? us[0] : cg1 ? us[2] : cg2 ? us[4] : us[6];
+            const float x1 = cg0 ? us[1] : cg1 ? us[3] : cg2 ? us[5] : us[7];
+            *(float2*)(rv.us + ((size_t)(it - 1) * RG + t.rg) * RT + 2 * t.cg) = make_float2(x0, x1);
         }
         // column half-step: v_k = b_k / sum_i Kt_ik u_i
         float p[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            float acc = 0.f;
+            float acc = kt[0][c] * us[0];
 #pragma unroll
-            for (int j = 0; j < RT; ++j) acc = fmaf(kt[j][c], wj[j], acc);
+            for (int j = 1; j < RT; ++j) acc = fmaf(kt[j][c], us[j], acc);
             p[c] = acc;
         }
         float z[Slots<CT>::H2];
@@ -391,7 +463,7 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
             vd = live ? 1.f : 0.f;
 #pragma unroll
             for (int j = 0; j < RT; ++j) {
-                ph[j] += (om[j] > 0.f) ? lg2(us[j]) : 0.f;
+                ph[j] += lg2(us[j]);
                 us[j] = 1.f;
             }
             float val[2] = {vd, gd}, out[2][CT];
@@ -402,6 +474,7 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
                 gam[c] = out[1][c];
             }
             tile_rebuild<CT, RT, W>(a.C, u, I, m, a.c2, t, off, gam, ph, kt);
+            if (store && it < a.T) put_stretch(it + 1);
         } else {
             float val[1] = {vd}, out[1][CT];
             spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
@@ -415,6 +488,8 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
                 put_hist(hist + (int64_t)(a.nck - 1) * a.hs);
         }
     }
+
+    if (store && threadIdx.x == 0) rv.sep[0] = nst;
 
     // epilogue: X = Kt v u, y_i = r_i sum_{k < m-1} e_k x_ik, potentials
     const int mo = m;
@@ -521,7 +596,13 @@ __device__ __forceinline__ void tile_reference(const float* C, int64_t u, int I,
     }
 }
 
-template <int CT, int RT, int W>
+// The reverse sweep.  STORED: the forward kept this consumer's row scalings
+// and the references of its stretches (RowStore); the sweep then works in the
+// forward's stretches, rebuilds each stretch's kernel from the stored
+// references (bit for bit the forward's) and takes u_i from the store instead
+// of forming the row sums sum_k Kt_ik w_k.  Otherwise it forms them and
+// chooses its own references (rebasing where a w leaves [2^-32, 2^32]).
+template <int CT, int RT, int W, bool STORED>
 __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
     extern __shared__ float smem[];
     if (a.stop && *a.stop) return;   // the outer loop has ended
@@ -538,6 +619,21 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
     const TileView tv = tile_view(tb, b, T, IP);
     const float* hist = a.hist + u * (int64_t)a.nck * a.hs;
     const int hs = a.hs;
+    const bool cg0 = t.cg == 0, cg1 = t.cg == 1, cg2 = t.cg == 2;
+    RowView rv{};
+    int f = 0, fstart = 1;   // STORED: the forward's stretch of the current iteration, its first iteration
+    float rhod_prev = 0.f;   // STORED: the column potential of stretch f - 1 (reducing lanes)
+    if constexpr (STORED) {
+        rv = row_view(a.rows, u, T, IP);
+        f = __builtin_amdgcn_readfirstlane(rv.sep[0]) - 1;
+        if (f >= kTileEpochs) {   // more stretches than the store keeps
+            if (threadIdx.x == 0) {
+                atomicOr(a.flags, FLAG_EPOCHS);
+                tv.ep[0] = 0;
+            }
+            return;
+        }
+    }
 
     float kt[RT][CT], off[RT], om[RT];
     tile_load<CT, RT, W>(a.C, u, I, m, a.c2, t, kt, off, om);
@@ -557,7 +653,7 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
 
     // segment of potentials gamma^{t0} .. gamma^{t1} in LDS (every iterate kept)
     int seg_t0 = -1;
-    auto load_seg = [&](int tt) {   // block containing gamma^{tt-1}, gamma^{tt}
+    auto load_seg = [&](int tt) __attribute__((always_inline)) {   // block containing gamma^{tt-1}, gamma^{tt}
         const int t0 = ((tt - 1) / kLoadBlock) * kLoadBlock;
         if (t0 == seg_t0) return;
         __syncthreads();
@@ -571,13 +667,12 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
     };
     auto gam_at = [&](int tt) { return seg[(tt - seg_t0) * 64 + (t.rcol >= 0 ? t.rcol : 0)]; };
 
-    // first stretch: reference rho = gamma^{T-1}
+    // A stretch of the sweep: reference column potentials rho (rhod on the
+    // reducing lanes) and row offsets phr; recorded for the contraction as
+    // stretch ne, which starts (in the sweep's order) at iteration tt.
     int ne = 0;
     float phr[RT];
-    auto new_stretch = [&](int tt) {
-        float val[1] = {live ? rhod : kNeg}, out[1][CT];
-        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
-        tile_reference<CT, RT, W>(a.C, u, I, m, a.c2, t, off, out[0], phr, kt);
+    auto record = [&](int tt) __attribute__((always_inline)) {
         const int e = ne < kTileEpochs ? ne : kTileEpochs - 1;
         if (ne >= kTileEpochs && threadIdx.x == 0) atomicOr(a.flags, FLAG_EPOCHS);
         if (t.w == 0 && t.rcol >= 0) tv.rho[e * 64 + t.rcol] = live ? rhod : 0.f;
@@ -587,32 +682,94 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
         if (threadIdx.x == 0) tv.ep[1 + e] = tt;
         ne = (ne < kTileEpochs) ? ne + 1 : ne;
     };
+    // own reference: rho = rhod, each row's largest entry at 1
+    auto new_stretch = [&](int tt) __attribute__((always_inline)) {
+        float val[1] = {live ? rhod : kNeg}, out[1][CT];
+        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        tile_reference<CT, RT, W>(a.C, u, I, m, a.c2, t, off, out[0], phr, kt);
+        record(tt);
+    };
+    // the forward's stretch f: its column potentials (kNeg on padded columns)
+    // and row offsets; rhod must hold its potential on the live columns
+    auto stored_stretch = [&](int tt) __attribute__((always_inline)) {
+        float val[1] = {t.rcol >= 0 ? rv.gam[f * 64 + t.rcol] : kNeg}, out[1][CT];
+        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        const float4* src = (const float4*)(rv.ph + ((size_t)f * RG + t.rg) * RT);
+#pragma unroll
+        for (int q = 0; q < RT / 4; ++q) {
+            const float4 x = src[q];
+            phr[4 * q] = x.x;
+            phr[4 * q + 1] = x.y;
+            phr[4 * q + 2] = x.z;
+            phr[4 * q + 3] = x.w;
+        }
+        tile_rebuild<CT, RT, W>(a.C, u, I, m, a.c2, t, off, out[0], phr, kt);
+        record(tt);
+        // (consumed here, so that no later wait for memory counts these loads)
+        fstart = __builtin_amdgcn_readfirstlane(rv.sep[1 + f]);
+        rhod_prev = opaque_f((f > 0 && live) ? rv.gam[(f - 1) * 64 + t.rcol] : 0.f);
+    };
+    // the forward's u_i of iteration tt (0 on rows beyond I)
+    auto load_u = [&](int tt, float (&x)[RT]) __attribute__((always_inline)) {
+        const float4* src = (const float4*)(rv.us + ((size_t)(tt - 1) * RG + t.rg) * RT);
+#pragma unroll
+        for (int q = 0; q < RT / 4; ++q) {
+            const float4 v4 = src[q];
+            x[4 * q] = v4.x;
+            x[4 * q + 1] = v4.y;
+            x[4 * q + 2] = v4.z;
+            x[4 * q + 3] = v4.w;
+        }
+    };
+
     load_seg(T);
-    rhod = live ? gam_at(T - 1) : 0.f;
-    new_stretch(T);
+    float ucur[RT], unext[RT];
+    if constexpr (STORED) {
+        rhod = live ? rv.gam[f * 64 + t.rcol] : 0.f;
+        stored_stretch(T);
+        load_u(T, ucur);
+    } else {
+        rhod = live ? gam_at(T - 1) : 0.f;   // first reference: rho = gamma^{T-1}
+        new_stretch(T);
+    }
+
+    // Column values of iteration T for the reducing lanes: w = 2^(gamma^{T-1}
+    // - rho) and xr = 2^(gamma^T - gamma^{T-1}) = b / sig^T; w spread to the
+    // lanes' columns (ow).
+    float wd, xr, ow[CT];
+    {
+        const float gp = live ? gam_at(T - 1) : kNeg, gq = live ? gam_at(T) : kNeg;
+        wd = live ? ex2(gp - rhod) : 0.f;
+        xr = live ? ex2(gq - gp) : 0.f;
+        float val[1] = {wd}, out[1][CT];
+        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) ow[c] = out[0][c];
+    }
 
     // initial term (t = T): X = P^T diag(b / sig^T); cbar = -G X / eps
     float fb0[RT];
+    float gmul;   // factor of the next team total: ev for the initial term, then -w
     {
-        const float gp = live ? gam_at(T - 1) : kNeg, gq = live ? gam_at(T) : kNeg;
-        const float wd = live ? ex2(gp - rhod) : 0.f;
-        const float xr = live ? ex2(gq - gp) : 0.f;
         const float ev = ekd * wd * xr;
-        float val[2] = {wd, ev}, out[2][CT];
-        spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        float val[1] = {ev}, out[1][CT];
+        spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
         float qr[RT];
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
             float s = 0.f, xe = 0.f;
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
-                s = fmaf(kt[j][c], out[0][c], s);
-                xe = fmaf(kt[j][c], out[1][c], xe);
+                if constexpr (!STORED) s = fmaf(kt[j][c], ow[c], s);
+                xe = fmaf(kt[j][c], out[0][c], xe);
             }
-            s = quad_sum(s);
             xe = quad_sum(xe);
-            const float qj = (om[j] > 0.f) ? a.inv_eps * rcp(s) : 0.f;   // 1 / (eps s_i)
-            const float xs = qj * xe;                                   // sum_k e_k x_ik / eps
+            float qj;   // 1 / (eps s_i)
+            if constexpr (STORED)
+                qj = (om[j] > 0.f) ? a.inv_eps * ucur[j] : 0.f;
+            else
+                qj = (om[j] > 0.f) ? a.inv_eps * rcp(quad_sum(s)) : 0.f;
+            const float xs = qj * xe;   // sum_k e_k x_ik / eps
             fb0[j] = rg[j] * xs;
             qr[j] = rg[j] * qj;
             const int i = j * RG + t.rg;
@@ -637,50 +794,116 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
         float z[Slots<CT>::H2];
         wave_colsum<CT>(p, z);
         put_partials<CT, W>(t, z, part);
-        __syncthreads();
-        gbar = ev * team_total<CT, W>(t, part);
+        gmul = ev;
     }
 
-    // reverse sweep t = T .. 1
-    int par = 1;
+    // reverse sweep t = T .. 1.  Each pass starts at the barrier that completes
+    // the previous pass's column partials; the team-total reads and the next
+    // pass's potentials are issued together, the row sums (which need only w)
+    // are formed while they are in flight, and the pass's w gh and the next
+    // pass's w are spread in one exchange.
+    int par = 0;
     for (int tt = T; tt >= 1; --tt) {
-        load_seg(tt);
-        const float gp = live ? gam_at(tt - 1) : kNeg, gq = live ? gam_at(tt) : kNeg;
-        float wd = live ? ex2(gp - rhod) : 0.f;
-        const bool bad = __builtin_amdgcn_ballot_w64(live && !(wd >= kScaleLo && wd <= kScaleHi)) != 0;
-        if (bad || (a.absorb > 0 && tt < T && (T - tt) % a.absorb == 0)) {
-            rhod = live ? gp : 0.f;
-            new_stretch(tt);
-            wd = live ? 1.f : 0.f;
+        __syncthreads();
+        const float* pp = part + par * 64 * W;
+        float x[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = pp[w * 64 + t.pslot];
+        const bool more = tt > 1;
+        const bool same_seg = more && tt - 2 >= seg_t0;
+        float gp_n = 0.f, gq_n = 0.f;
+        if (same_seg) {
+            gp_n = live ? gam_at(tt - 2) : kNeg;
+            gq_n = live ? gam_at(tt - 1) : kNeg;
         }
-        const float gh = live ? gbar * ex2(gq - gp) * ibc : 0.f;   // gbar / sig^t
+        if constexpr (STORED) {
+            if (more) load_u(tt - 1, unext);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float uj[RT];
+        if constexpr (STORED) {
+#pragma unroll
+            for (int j = 0; j < RT; ++j) uj[j] = (om[j] > 0.f) ? ucur[j] : 0.f;
+        } else {
+            float sr[RT];
+#pragma unroll
+            for (int j = 0; j < RT; ++j) sr[j] = 0.f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int j = 0; j < RT; ++j) sr[j] = fmaf(kt[j][c], ow[c], sr[j]);
+#pragma unroll
+            for (int j = 0; j < RT; ++j) uj[j] = (om[j] > 0.f) ? rcp(quad_sum(sr[j])) : 0.f;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float tot = 0.f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) tot += x[w];
+        gbar = gmul * tot;
+        const float gh = live ? gbar * xr * ibc : 0.f;   // gbar / sig^t
         const float wg = wd * gh;
-        float val[2] = {wd, wg}, out[2][CT];
-        spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+        // the next pass's column values (a new stretch is started after this
+        // pass's column sums, which still need the current reference)
+        float wd_n = 0.f, xr_n = 0.f, rhod_n = rhod;
+        bool restart = false;
+        if (more) {
+            if (!same_seg) {
+                load_seg(tt - 1);
+                gp_n = live ? gam_at(tt - 2) : kNeg;
+                gq_n = live ? gam_at(tt - 1) : kNeg;
+            }
+            if constexpr (STORED) {
+                restart = tt - 1 < fstart;   // iteration tt - 1 lies in the forward's stretch f - 1
+                if (restart) rhod_n = rhod_prev;
+                wd_n = live ? ex2(gp_n - rhod_n) : 0.f;
+            } else {
+                wd_n = live ? ex2(gp_n - rhod) : 0.f;
+                restart = __builtin_amdgcn_ballot_w64(live && !(wd_n >= kScaleLo && wd_n <= kScaleHi)) != 0 ||
+                          (a.absorb > 0 && (T - tt + 1) % a.absorb == 0);
+            }
+            xr_n = live ? ex2(gq_n - gp_n) : 0.f;
+        }
+        float og[CT], ow_n[CT];
+        {
+            float val[2] = {wg, wd_n}, out[2][CT];
+            spread_cols<CT, 2>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                og[c] = out[0][c];
+                ow_n[c] = out[1][c];
+            }
+        }
         float aa[RT];
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
-            float s = 0.f, d = 0.f;
+            float d = 0.f;
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                s = fmaf(kt[j][c], out[0][c], s);
-                d = fmaf(kt[j][c], out[1][c], d);
-            }
-            s = quad_sum(s);
+            for (int c = 0; c < CT; ++c) d = fmaf(kt[j][c], og[c], d);
             d = quad_sum(d);
-            const float uj = (om[j] > 0.f) ? rcp(s) : 0.f;
-            const float fb = (tt == T ? fb0[j] : 0.f) - uj * d;
-            aa[j] = uj * fb;
-            const int i = j * RG + t.rg;
-            if (t.cg == (j & 3)) {
-                tv.A[(size_t)((tt - 1) * 2 + 0) * IP + i] = uj;
-                tv.A[(size_t)((tt - 1) * 2 + 1) * IP + i] = aa[j];
-            }
+            const float fb = (tt == T ? fb0[j] : 0.f) - uj[j] * d;
+            aa[j] = uj[j] * fb;
+        }
+        // lane cg of the quad stores rows cg and cg + 4, selected without a
+        // branch: every lane issues the same stores, so that the wait for a
+        // load issued earlier in the pass can count them
+        {
+            static_assert(RT == 8, "rows cg and cg + 4 of a quad's eight");
+            const float u0 = cg0 ? uj[0] : cg1 ? uj[1] : cg2 ? uj[2] : uj[3];
+            const float u1 = cg0 ? uj[4] : cg1 ? uj[5] : cg2 ? uj[6] : uj[7];
+            const float a0 = cg0 ? aa[0] : cg1 ? aa[1] : cg2 ? aa[2] : aa[3];
+            const float a1 = cg0 ? aa[4] : cg1 ? aa[5] : cg2 ? aa[6] : aa[7];
+            float* A0 = tv.A + (size_t)((tt - 1) * 2 + 0) * IP + t.cg * RG + t.rg;
+            float* A1 = tv.A + (size_t)((tt - 1) * 2 + 1) * IP + t.cg * RG + t.rg;
+            A0[0] = u0;
+            A1[0] = a0;
+            A0[4 * RG] = u1;
+            A1[4 * RG] = a1;
         }
         if (t.w == 0 && t.rcol >= 0) {
             tv.B[(size_t)((tt - 1) * 2 + 0) * 64 + t.rcol] = wg;
             tv.B[(size_t)((tt - 1) * 2 + 1) * 64 + t.rcol] = wd;
         }
+        if (!more) break;   // gbar after the first iteration is not needed
         float p[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -691,11 +914,30 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
         }
         float z[Slots<CT>::H2];
         wave_colsum<CT>(p, z);
-        float* pp = part + par * 64 * W;
-        put_partials<CT, W>(t, z, pp);
-        __syncthreads();
-        gbar = -wd * team_total<CT, W>(t, pp);
         par ^= 1;
+        put_partials<CT, W>(t, z, part + par * 64 * W);
+        gmul = -wd;
+        wd = wd_n;
+        xr = xr_n;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) ow[c] = ow_n[c];
+        if constexpr (STORED) {
+#pragma unroll
+            for (int j = 0; j < RT; ++j) ucur[j] = unext[j];
+            if (restart) {
+                --f;
+                rhod = rhod_n;
+                stored_stretch(tt - 1);
+            }
+        } else if (restart) {
+            rhod = live ? gp_n : 0.f;
+            new_stretch(tt - 1);
+            wd = live ? 1.f : 0.f;
+            float val[1] = {wd}, out[1][CT];
+            spread_cols<CT, 1>(vb, t.rslot, t.rcol >= 0, val, t.cg, out);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) ow[c] = out[0][c];
+        }
     }
     if (threadIdx.x == 0) tv.ep[0] = ne;
 }
@@ -922,8 +1164,12 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
     const TileBuf& tb = a.tile;
     for (int64_t u0 = 0; u0 < a.U; u0 += tb.batch) {
         const int nb = (int)((a.U - u0) < tb.batch ? (a.U - u0) : tb.batch);
-        hipLaunchKernelGGL((k_tbwd<CT, RT, W>), dim3(nb), dim3(64 * W),
-                           tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
+        if (a.rows.base && u0 + nb <= a.rows.n)   // the forward kept these consumers' row scalings
+            hipLaunchKernelGGL((k_tbwd<CT, RT, W, true>), dim3(nb), dim3(64 * W),
+                               tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
+        else
+            hipLaunchKernelGGL((k_tbwd<CT, RT, W, false>), dim3(nb), dim3(64 * W),
+                               tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
         constexpr int NRB = (IP + 255) / 256;
         const int groups = (nb + kXcds - 1) / kXcds;
         if (!a.dC && !a.Cw) continue;
@@ -959,6 +1205,15 @@ const TileEntry* tile_entry(int m, int I) {
     for (const TileShape& t : kTileShapes)
         if (m >= t.mmin && m <= t.e.cmax && I <= t.e.imax && I > t.e.imin) return &t.e;
     return nullptr;
+}
+
+size_t tile_row_bytes(const TileEntry* e, int T) {
+    const size_t IP = (size_t)e->imax;
+    size_t o = sizeof(float) * (size_t)T * IP;
+    o += sizeof(float) * (size_t)kTileEpochs * IP;
+    o += sizeof(float) * (size_t)kTileEpochs * 64;
+    o += sizeof(int) * (size_t)(kTileEpochs + 1);
+    return (o + 255) / 256 * 256;
 }
 
 size_t tile_consumer_bytes(const TileEntry* e, int T) {

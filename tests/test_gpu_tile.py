@@ -1,11 +1,12 @@
 """Tile kernels of large plans (512 < |I| <= 1024 items, 40 <= m <= 50
 columns; the 100000 x 1000 x 50 workload's plans): scaling-form forward on
 2-D lane tiles, and the reverse sweep whose cost adjoint is contracted on the
-matrix cores from per-iteration row and column factors.  Parity with the FP64
-oracle (Section 3 forward and chain rule, Eqs. Imp and objF), with the
-reference kernel rebased on range and by a forced period (several stretches
-per consumer), Adam and plain-ascent trajectories, and the error raised when
-a consumer needs more stretches than the sweep keeps."""
+matrix cores from per-iteration row and column factors, with the row
+scalings kept by the forward (row store, the default) or formed by the sweep.
+Parity with the FP64 oracle (Section 3 forward and chain rule, Eqs. Imp and
+objF), with the reference kernel rebased on range and by a forced period
+(several stretches per consumer), Adam and plain-ascent trajectories, and the
+error raised when a consumer needs more stretches than the sweep keeps."""
 import numpy as np
 import pytest
 import torch
@@ -20,9 +21,10 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(3, 1000, 50), (2, 1024, 48), (4, 513, 40), (2, 700, 41)]
 
 
-def _ctx(fr, absorb=0):
+def _ctx(fr, absorb=0, store=True):
     ctx = fr.Context(0)
     ctx.set_form("scaling", absorb)
+    ctx.set_row_store(store)
     return ctx
 
 
@@ -52,12 +54,14 @@ def test_tile_forward_matches_oracle(fr, U, I, m, absorb):
 
 @pytest.mark.parametrize("U,I,m", SHAPES)
 @pytest.mark.parametrize("absorb", [0, 5])
-def test_tile_backward_matches_oracle(fr, U, I, m, absorb):
+@pytest.mark.parametrize("store", [True, False])
+def test_tile_backward_matches_oracle(fr, U, I, m, absorb, store):
     """dF/dC and dF/dr through the T unrolled iterations; absorb = 5 rebases
-    the reverse sweep's reference every 5 iterations (12 stretches at T = 60)."""
-    print(f"case tile backward U={U} I={I} m={m} absorb={absorb}", flush=True)
+    the reference every 5 iterations (12 stretches at T = 60): the forward's
+    with the row store, the sweep's own without it."""
+    print(f"case tile backward U={U} I={I} m={m} absorb={absorb} store={store}", flush=True)
     inst = W.small_instance(U, I, m, seed=I + m + 1, eps=0.02, T=60, kind="lowrank")
-    ctx = _ctx(fr, absorb)
+    ctx = _ctx(fr, absorb, store)
     prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
     C = W.random_costs(U, I, m, 0.04, seed=I + 1)
     Cd = torch.from_numpy(C).cuda()
@@ -84,13 +88,14 @@ def test_tile_backward_scales_with_gF(fr):
 
 
 @pytest.mark.parametrize("rule", ["gd", "adam"])
-def test_tile_solve_matches_oracle(fr, rule):
+@pytest.mark.parametrize("store", [True, False])
+def test_tile_solve_matches_oracle(fr, rule, store):
     """Algorithm 1 on tile plans: GD is well conditioned (costs and plans to
     1e-5); Adam is compared through F and the forward at the GPU's own C."""
     U, I, m, T, N = 4, 600, 40, 40, 5
-    print(f"case tile solve {rule}", flush=True)
+    print(f"case tile solve {rule} store={store}", flush=True)
     inst = W.small_instance(U, I, m, seed=11, eps=0.03, T=T, kind="lowrank")
-    ctx = _ctx(fr)
+    ctx = _ctx(fr, 0, store)
     prob = device_problem(fr, inst.r, inst.e, inst.eps, T)
     lr = 0.002 if rule == "gd" else 0.003   # GD: F rises monotonically (oracle)
     res = fr.solve(ctx, prob, N, lr, rule=rule)
@@ -136,13 +141,41 @@ def test_tile_matches_pinned_kernels(fr):
     assert float(torch.max(torch.abs(dt - dp))) <= GRAD_REL * float(torch.max(torch.abs(dp)))
 
 
-def test_tile_too_many_stretches_is_reported(fr):
-    """Rebasing the reverse sweep every iteration for T = 30 > 16 stretches:
-    the sweep keeps 16 and the solve reports FR_E_UNSUPPORTED (8)."""
+@pytest.mark.parametrize("store", [True, False])
+def test_tile_too_many_stretches_is_reported(fr, store):
+    """Rebasing every iteration for T = 30 > 16 stretches (the forward's, kept
+    in the row store, or the sweep's own): the solve reports
+    FR_E_UNSUPPORTED (8)."""
     U, I, m = 2, 600, 40
     inst = W.small_instance(U, I, m, seed=15, eps=0.03, T=30, kind="lowrank")
-    ctx = _ctx(fr, 1)
+    ctx = _ctx(fr, 1, store)
     prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
     with pytest.raises(fr.FairRankError) as ex:
         fr.solve(ctx, prob, 1, 0.003)
     assert ex.value.code == 8
+    ctx = _ctx(fr, 1, store)   # a fresh workspace: device flags stay set until read
+    Cd = torch.from_numpy(W.random_costs(U, I, m, 0.05, seed=16)).cuda()
+    out = fr.step(ctx, prob, Cd)
+    with pytest.raises(fr.FairRankError) as ex:
+        fr.backward(ctx, prob, Cd, out["imp"], 1.0, want_dr=False, K=1)
+    assert ex.value.code == 8
+
+
+@pytest.mark.parametrize("absorb", [0, 7])
+def test_tile_row_store_matches_sweep_own_rows(fr, absorb):
+    """The reverse sweep with the forward's row scalings and stretches against
+    the sweep that forms them (and its own stretches): the same gradient to
+    the FP32 bars, on a consumer count that spans several blocks."""
+    U, I, m = 9, 1000, 50
+    print(f"case tile row store vs own rows absorb={absorb}", flush=True)
+    inst = W.small_instance(U, I, m, seed=21, eps=0.01, T=100, kind="lowrank")
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, inst.T)
+    Cd = torch.from_numpy(W.random_costs(U, I, m, 0.02, seed=22)).cuda()
+    s, o = _ctx(fr, absorb, True), _ctx(fr, absorb, False)
+    out = fr.step(s, prob, Cd)
+    ds, rs = fr.backward(s, prob, Cd, out["imp"], 1.0, want_dr=True, K=1)
+    do, ro = fr.backward(o, prob, Cd, out["imp"], 1.0, want_dr=True, K=1)
+    cerr = float(torch.max(torch.abs(ds - do)) / torch.max(torch.abs(do)))
+    rerr = float(torch.max(torch.abs(rs - ro)) / torch.max(torch.abs(ro)))
+    print(f"  dC {cerr:.3e} of max, dr {rerr:.3e} of max", flush=True)
+    assert cerr <= GRAD_REL and rerr <= 1e-5
