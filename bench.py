@@ -736,19 +736,70 @@ def bench_batched(args, fr, lib, dev):
     # the same instances solved one after another by the single-instance
     # fused solver (no batching), at equal T and N
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Fs = []
+    Fs, secs = [], []
     for p in probs:
+        t1 = time.perf_counter()
         r1 = fr.solve(ctx, p, N, lr, want_X=False)
-        Fs.append(r1["F_hist"].cpu().numpy())
+        Fs.append(r1["F_hist"].cpu().numpy())   # (synchronises)
+        secs.append(time.perf_counter() - t1)
         del r1
-    torch.cuda.synchronize()
-    sdt = time.perf_counter() - t0
+    sdt = float(sum(secs))
+    # where the sequential time goes: instances whose own solve already runs
+    # at (nearly) the best rate any instance reaches gain nothing from sharing
+    # the device; the bound below is the time if every instance ran at that rate
+    wk = np.array([x.cells * T * N for x in insts], dtype=np.float64)
+    rate = wk / np.array(secs)
+    best = float(np.max(rate))
+    full = rate >= 0.8 * best
+    by_m = {}
+    for x, sj, wj in zip(insts, secs, wk):
+        key = "m<=10" if x.m <= 10 else ("m<=25" if x.m <= 25 else "m>25")
+        e = by_m.setdefault(key, {"instances": 0, "seconds": 0.0, "cell_iters": 0.0})
+        e["instances"] += 1
+        e["seconds"] += sj
+        e["cell_iters"] += wj
     out["sequential_fused"] = {"value": work / sdt, "ms_per_step": sdt * 1e3,
                                "batched_speedup": sdt / dt,
                                "F_rel_diff_max": float(max(np.max(np.abs(a / b - 1))
-                                                           for a, b in zip(Fb, Fs)))}
-    print(f"bench: sequential fused {sdt:.2f} s", flush=True)
+                                                           for a, b in zip(Fb, Fs))),
+                               "best_instance_rate": best,
+                               "share_of_time_in_instances_at_80pct_of_best": float(
+                                   np.sum(np.array(secs)[full]) / sdt),
+                               "seconds_if_all_at_best_rate": float(np.sum(wk) / best),
+                               "speedup_bound_vs_sequential": float(sdt / (np.sum(wk) / best)),
+                               "by_columns": by_m}
+    # each instance's plan shape on a full device: one outer step with 8192
+    # consumers (its relevance rows repeated), timed as the difference of a
+    # 3-step and a 1-step solve; the batched solve cannot beat running every
+    # instance at its shape's saturated rate
+    sat = []
+    for x, p in zip(insts, probs):
+        Us = 8192
+        rs = torch.from_numpy(np.resize(x.r, (Us, x.I))).to(dev)
+        ps = fr.Problem(rs, p.e, float(x.eps), T)
+        fr.solve(ctx, ps, 1, lr, want_X=False)
+        ts = []
+        for n in (1, 3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fr.solve(ctx, ps, n, lr, want_X=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        sat.append(Us * x.I * x.m * T / max((ts[1] - ts[0]) / 2, 1e-9))
+        del rs, ps
+    sat = np.array(sat)
+    ideal = float(np.sum(wk / sat))
+    out["sequential_fused"].update({
+        "saturated_shape_rates": "each instance's (I, m) at 8192 consumers, one outer step",
+        "seconds_if_each_at_its_saturated_rate": ideal,
+        "batched_vs_that": dt / ideal, "sequential_vs_that": sdt / ideal,
+        "per_instance": [[x.U, x.I, x.m, round(sj, 4), float(f"{r:.4g}")]
+                         for x, sj, r in zip(insts, secs, sat)]})
+    print(f"bench: every instance at its shape's saturated rate: {ideal:.2f} s "
+          f"(batched {dt / ideal:.2f}x, sequential {sdt / ideal:.2f}x of it)", flush=True)
+    print(f"bench: sequential fused {sdt:.2f} s; best instance rate {best:.3e}; "
+          f"{100 * np.sum(np.array(secs)[full]) / sdt:.0f}% of the time in instances within 80% "
+          f"of it; all at that rate: {np.sum(wk) / best:.2f} s", flush=True)
     if not args.skip_plain:
         sub = list(range(0, 128, 16))   # 8 instances
         t0 = time.perf_counter()

@@ -177,8 +177,10 @@ struct Shape {
 // reduce-scatter of wave-wide teams, plus an LDS exchange for teams of
 // several waves.  Each of the 1024 SIMDs runs its share of the waves back to
 // back, and a SIMD with a single wave hides its latencies poorly.
-double model_cost(int64_t U, int mp, int L, const FusedEntry& e) {
-    const double cell = (e.recomp_f ? 7.0 : 5.0) + (e.recomp_b ? 11.0 : 8.0);
+// scaling: both kernels run the scaling form (no recompute pass), about
+// 2.5 VALU operations per cell fewer than the log domain (measured).
+double model_cost(int64_t U, int mp, int L, const FusedEntry& e, bool scaling = false) {
+    const double cell = scaling ? 10.5 : (e.recomp_f ? 7.0 : 5.0) + (e.recomp_b ? 11.0 : 8.0);
     double red;
     if (L < 64) {
         int lv = 0;
@@ -534,7 +536,8 @@ fr_status read_flags(WsHeader* h, hipStream_t s, bool clear) {
 
 // ---------------------------------------------------------------- batched
 // Launch shape of one instance inside the persistent kernels: blocks of 256
-// threads, teams of L <= 256 lanes, LDS within 64 KB.
+// threads with teams of L <= 256 lanes, or of 512 threads with one team of
+// 512 lanes (one row per lane), LDS within 64 KB.
 struct BatchShape {
     const FusedEntry* fe;
     int L, R, mp, teams;
@@ -546,12 +549,14 @@ fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
     const int mp = reg.mp_for(m);
     if (mp < 0) return FR_E_UNSUPPORTED;
     const int BL = (K <= 1) ? kLoadBlock : K;
+    // blocks of 256 threads (teams of up to 256 lanes) or of 512 (one team)
     auto fits = [&](int L, int R, const FusedEntry** fe_out, size_t* lf, size_t* lb) {
-        if (!lanes_ok(L) || L > 256 || 256 % L != 0 || (int64_t)L * R < I) return false;
-        const FusedEntry* fe = reg.pick(mp, R, L, 256);
-        if (!fe) return false;
+        const int block = L <= 256 ? 256 : 512;
+        if (!lanes_ok(L) || L > 512 || block % L != 0 || (int64_t)L * R < I) return false;
+        const FusedEntry* fe = reg.pick(mp, R, L, block);
+        if (!fe || !fe->bfwd) return false;
         const int W = (L + 63) / 64;
-        const int teams = 256 / L;
+        const int teams = block / L;
         const size_t per_b = (size_t)((BL + 1) * mp + 2 * W * mp) * sizeof(float);
         if (teams * per_b > kMaxLds) return false;
         *fe_out = fe;
@@ -564,26 +569,28 @@ fr_status batch_shape(fr_ctx* ctx, int I, int m, int K, BatchShape* bs) {
         const FusedEntry* fe;
         size_t lf, lb;
         if (fits(it->second.first, it->second.second, &fe, &lf, &lb)) {
-            *bs = BatchShape{fe, it->second.first, it->second.second, mp, 256 / it->second.first, lf, lb};
+            *bs = BatchShape{fe, it->second.first, it->second.second, mp, fe->lb / it->second.first, lf, lb};
             return FR_OK;
         }
     }
     double best = 1e300;
     bool found = false;
-    const int Ls[] = {8, 16, 32, 64, 128, 256};
+    const int Ls[] = {8, 16, 32, 64, 128, 256, 512};
     for (int L : Ls) {
         for (auto& e : reg.all) {
-            if (e.mp != mp || e.lb != 256 || e.wide != (L >= 64)) continue;
+            if (e.mp != mp || e.lb != (L <= 256 ? 256 : 512) || e.wide != (L >= 64) || !e.bfwd) continue;
             const int R = e.rows;
             if ((int64_t)L * (R - 1) >= I) continue;
             const FusedEntry* fe;
             size_t lf, lb;
             if (!fits(L, R, &fe, &lf, &lb)) continue;
             // the batch as a whole fills the device: cost in the saturated regime
-            const double c = model_cost((int64_t)1 << 20, mp, L, *fe);
+            const bool sc = ctx->form == FR_FORM_SCALING && K <= 1 && fe->bbwds && !fe->recomp_b &&
+                            !fe->recomp_f;
+            const double c = model_cost((int64_t)1 << 20, mp, L, *fe, sc);
             if (c < best) {
                 best = c;
-                *bs = BatchShape{fe, L, R, mp, 256 / L, lf, lb};
+                *bs = BatchShape{fe, L, R, mp, fe->lb / L, lf, lb};
                 found = true;
             }
         }
@@ -1490,9 +1497,10 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
     for (int c = 0; c < ncls; ++c) {
         const int nit = (int)P.items[c].size();
         const Occupancy occ_f = scaling ? P.classes[c]->occ_bfwds : P.classes[c]->occ_bfwd;
-        grid_f[c] = std::max(1, std::min(nit, occ_f(256, P.lds_fwd[c]) * cus));
+        const int blk = P.classes[c]->lb;
+        grid_f[c] = std::max(1, std::min(nit, occ_f(blk, P.lds_fwd[c]) * cus));
         const Occupancy occ_b = sweep_s[c] ? P.classes[c]->occ_bbwds : P.classes[c]->occ_bbwd;
-        grid_b[c] = std::max(1, std::min(nit, occ_b(256, P.lds_bwd[c]) * cus));
+        grid_b[c] = std::max(1, std::min(nit, occ_b(blk, P.lds_bwd[c]) * cus));
     }
     // The column classes of a phase share nothing (own work lists, counters and
     // outputs), so they run concurrently: forked from s onto the side streams
@@ -1525,8 +1533,8 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 0);
         run_classes([&](int c, hipStream_t sc) {
             (scaling ? P.classes[c]->bfwds : P.classes[c]->bfwd)(
-                descs, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_f[c], 256,
-                P.lds_fwd[c], sc);
+                descs, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_f[c],
+                P.classes[c]->lb, P.lds_fwd[c], sc);
         });
         launch_impact_batched(drd, n_inst, dt1, (int)P.tab1.size(), dt2, (int)P.tab2.size(),
                               start_step, hdr, s);
@@ -1535,8 +1543,8 @@ fr_status fr_solve_batched(fr_ctx* ctx, int32_t n_inst, const fr_problem* probs,
         hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(64), 0, s, hdr, counters, ncls, 1);
         run_classes([&](int c, hipStream_t sc) {
             (sweep_s[c] ? P.classes[c]->bbwds : P.classes[c]->bbwd)(
-                dba, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_b[c], 256,
-                P.lds_bwd[c], sc);
+                dba, ditems + item_off[c], (int)P.items[c].size(), counters + c, grid_b[c],
+                P.classes[c]->lb, P.lds_bwd[c], sc);
         });
     };
 
@@ -1606,13 +1614,15 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
     if (!batched && tile_entry(p.m, I) && ctx->form == FR_FORM_SCALING) cands.push_back({512, 0});
     const int Ls[] = {8, 16, 32, 64, 128, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024};
     for (int L : Ls) {
-        if (batched && (L > 256 || 256 % L != 0)) continue;
+        // the batched kernels' blocks: 256 threads, or 512 for one team of 512 lanes
+        const int bblk = L <= 256 ? 256 : 512;
+        if (batched && (L > 512 || bblk % L != 0)) continue;
         for (auto& e : reg.all) {
             if (e.mp != mp) continue;
             const int R = e.rows;
             if ((int64_t)L * R < I || (int64_t)L * (R - 1) >= I) continue;
-            if (&e != reg.pick(mp, R, L, batched ? 256 : block_for(L))) continue;
-            if (batched && R * mp > 128) continue;
+            if (&e != reg.pick(mp, R, L, batched ? bblk : block_for(L))) continue;
+            if (batched && (R * mp > 128 || !e.bfwd)) continue;
             cands.push_back({L, R});
         }
     }
@@ -1622,7 +1632,8 @@ fr_status fr_autotune(fr_ctx* ctx, const fr_problem* prob, const float* C, int32
             ctx->launch[{I, p.m}] = {L, R};
             Shape sh;
             if (make_shape(ctx, p.n_users, I, p.m, 1, &sh) != FR_OK) continue;
-            if (R > 0 && (sh.te || sh.fe != reg.pick(mp, R, L, batched ? 256 : block_for(L))))
+            if (R > 0 && (sh.te || sh.fe != reg.pick(mp, R, L, batched ? (L <= 256 ? 256 : 512)
+                                                                       : block_for(L))))
                 continue;
             FwdArgs a = fwd_args(&p, sh, C);
             a.y = (float*)(w + Lw.y);

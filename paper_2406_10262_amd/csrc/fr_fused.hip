@@ -1968,8 +1968,10 @@ __global__ __launch_bounds__(LB) void k_ibwd(BwdArgs a) {
 // Persistent batched kernels: every block repeatedly takes the next work item
 // (instance, first consumer) from a global counter and runs the same team
 // body on it, until the list is exhausted.  Items are ordered longest first.
-template <int MP, int R, bool WIDE, bool SCALE>
-__global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
+// Blocks of LB threads: 256 (several teams of up to 256 lanes) or 512 (one
+// team of 512 lanes).
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
+__global__ __launch_bounds__(LB) void k_bfwd(const FwdArgs* __restrict__ descs,
                                               const BatchItem* __restrict__ items, int n_items,
                                               unsigned* counter) {
     extern __shared__ float smem[];
@@ -1985,12 +1987,12 @@ __global__ __launch_bounds__(256) void k_bfwd(const FwdArgs* __restrict__ descs,
         if constexpr (SCALE)
             fwds_body<MP, R, WIDE>(a, bi.u0, smem);
         else
-            fwd_body<MP, R, WIDE, recomp_fwd<R, 256, WIDE>()>(a, bi.u0, smem);
+            fwd_body<MP, R, WIDE, recomp_fwd<R, LB, WIDE>()>(a, bi.u0, smem);
     }
 }
 
-template <int MP, int R, bool WIDE, bool SCALE>
-__global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
+__global__ __launch_bounds__(LB) void k_bbwd(const BwdArgs* __restrict__ descs,
                                               const BatchItem* __restrict__ items, int n_items,
                                               unsigned* counter) {
     extern __shared__ float smem[];
@@ -2004,37 +2006,37 @@ __global__ __launch_bounds__(256) void k_bbwd(const BwdArgs* __restrict__ descs,
         const BatchItem bi = items[it];
         const BwdArgs a = descs[bi.inst];
         if constexpr (SCALE)
-            bwds_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
+            bwds_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, bi.u0, smem);
         else
-            bwd_body<MP, R, WIDE, recomp_bwd<R, 256, WIDE>()>(a, bi.u0, smem);
+            bwd_body<MP, R, WIDE, recomp_bwd<R, LB, WIDE>()>(a, bi.u0, smem);
     }
 }
 
-template <int MP, int R, bool WIDE, bool SCALE>
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
 void launch_bfwd(const FwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bfwd<MP, R, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
+    hipLaunchKernelGGL((k_bfwd<MP, R, LB, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
                        ctr);
 }
-template <int MP, int R, bool WIDE, bool SCALE>
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
 void launch_bbwd(const BwdArgs* d, const BatchItem* it, int n, unsigned* ctr, int grid, int block,
                  size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_bbwd<MP, R, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
+    hipLaunchKernelGGL((k_bbwd<MP, R, LB, WIDE, SCALE>), dim3(grid), dim3(block), lds, s, d, it, n,
                        ctr);
 }
-template <int MP, int R, bool WIDE, bool SCALE>
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
 int occupancy_bfwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, WIDE, SCALE>, block, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bfwd<MP, R, LB, WIDE, SCALE>, block,
+                                                     lds) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
-template <int MP, int R, bool WIDE, bool SCALE>
+template <int MP, int R, int LB, bool WIDE, bool SCALE>
 int occupancy_bbwd(int block, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, WIDE, SCALE>, block, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_bbwd<MP, R, LB, WIDE, SCALE>, block,
+                                                     lds) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
@@ -2070,7 +2072,7 @@ void launch_ibwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
 
 template <int R, int LB, bool WIDE>
 constexpr FusedEntry entry() {
-    if constexpr (LB == 256) {
+    if constexpr (LB == 256 || (LB == 512 && R == 1)) {
         return FusedEntry{FR_MP,
                           R,
                           LB,
@@ -2082,17 +2084,18 @@ constexpr FusedEntry entry() {
                           &launch_fwdc<FR_MP, R, LB, WIDE>,
                           &launch_ibwd<FR_MP, R, LB, WIDE>,
                           &launch_fwds<FR_MP, R, LB, WIDE>,
-                          &launch_bfwd<FR_MP, R, WIDE, false>,
-                          &launch_bbwd<FR_MP, R, WIDE, false>,
-                          &occupancy_bfwd<FR_MP, R, WIDE, false>,
-                          &occupancy_bbwd<FR_MP, R, WIDE, false>,
-                          &launch_bfwd<FR_MP, R, WIDE, true>,
-                          &occupancy_bfwd<FR_MP, R, WIDE, true>,
+                          &launch_bfwd<FR_MP, R, LB, WIDE, false>,
+                          &launch_bbwd<FR_MP, R, LB, WIDE, false>,
+                          &occupancy_bfwd<FR_MP, R, LB, WIDE, false>,
+                          &occupancy_bbwd<FR_MP, R, LB, WIDE, false>,
+                          &launch_bfwd<FR_MP, R, LB, WIDE, true>,
+                          &occupancy_bfwd<FR_MP, R, LB, WIDE, true>,
                           &launch_bwds<FR_MP, R, LB, WIDE>,
-                          &launch_bbwd<FR_MP, R, WIDE, true>,
-                          &occupancy_bbwd<FR_MP, R, WIDE, true>,
-                          nullptr,
-                          0};
+                          &launch_bbwd<FR_MP, R, LB, WIDE, true>,
+                          &occupancy_bbwd<FR_MP, R, LB, WIDE, true>,
+                          LB == 512 && cb_lds_rows<R, LB, WIDE>() > 0 ? &launch_bwdl<FR_MP, R, LB, WIDE>
+                                                                      : nullptr,
+                          LB == 512 ? cb_lds_rows<R, LB, WIDE>() : 0};
     } else {
         return FusedEntry{FR_MP, R, LB, WIDE, recomp_fwd<R, LB, WIDE>(), recomp_bwd<R, LB, WIDE>(),
                           &launch_fwd<FR_MP, R, LB, WIDE>, &launch_bwd<FR_MP, R, LB, WIDE>,

@@ -117,7 +117,7 @@ struct FusedEntry {
     FwdLaunch fwdc;     // converged-map forward (warm start, tolerance)
     BwdLaunch ibwd;     // implicit-function gradient at a converged plan
     FwdLaunch fwds;     // scaling-form forward (same iterates as fwd)
-    BFwdLaunch bfwd;    // persistent batched forms (launch bound 256 only)
+    BFwdLaunch bfwd;    // persistent batched forms (launch bound 256, and 512 with one row)
     BBwdLaunch bbwd;
     Occupancy occ_bfwd;
     Occupancy occ_bbwd;
