@@ -372,6 +372,10 @@ fr_status check_problem(const fr_problem* p) {
 
 int resolve_k(int K) { return K <= 0 ? 1 : K; }
 
+// A checkpoint interval beyond T means one segment of T iterations (the same
+// checkpoints); the segment buffers are sized by the clamped interval.
+int clamp_k(int K, int T) { return K <= 1 ? K : std::max(2, std::min(K, T)); }
+
 struct PlainLayout {
     size_t hdr, imp, partial, y, fh, gh, cbar, fbar, fbar0, gbar, gpart, total;
     int nchunk;
@@ -975,7 +979,7 @@ fr_status fr_backward(fr_ctx* ctx, const fr_problem* prob, const float* C, const
     if (st) return st;
     if (!C || !imp || !dC || !ws) return FR_E_NULL;
     if (checkpoint_every < 1 || !isfinite(gF)) return FR_E_PARAM;
-    const int K = checkpoint_every;
+    const int K = clamp_k(checkpoint_every, prob->sinkhorn_iters);
     const Layout Lw = layout(prob, K);
     if (ws_bytes < Lw.total) return FR_E_WORKSPACE;
     Shape sh;
@@ -1009,7 +1013,7 @@ fr_status fr_solve(fr_ctx* ctx, const fr_problem* prob, const fr_optim* optim, f
     if ((st = check_optim(optim, adam_m, adam_v, start_step))) return st;
     if (!C || !F_hist || !ws) return FR_E_NULL;
     if (x_dtype != FR_F32 && x_dtype != FR_BF16) return FR_E_PARAM;
-    const int K = resolve_k(optim->checkpoint_every);
+    const int K = clamp_k(resolve_k(optim->checkpoint_every), prob->sinkhorn_iters);
     const bool tol = optim->grad_tol > 0.0;
     const bool conv = optim->sinkhorn_tol > 0.f;
     const Layout Lw = layout(prob, K, tol, conv);

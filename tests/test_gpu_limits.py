@@ -96,3 +96,28 @@ def test_plans_beyond_the_registers_are_unsupported(fr):
     res = fr.solve_plain(ctx, prob, 1, 0.01, rule="gd")
     ref = oracle.solve(inst.r, inst.e, float(inst.eps), 5, 1, rule="gd", lr=0.01)
     assert np.max(np.abs(res["F_hist"].cpu().numpy() / ref["F_hist"] - 1)) <= 1e-6
+
+
+@pytest.mark.parametrize("form", ["scaling", "log"])
+@pytest.mark.parametrize("K", [7, 50])
+def test_checkpointed_sweep_with_cost_adjoints_in_lds(fr, form, K):
+    """The reverse sweep that rebuilds each segment of K iterations from its
+    checkpoint, on the 1000 x 50 plans at the (512, 2) launch, where it keeps
+    one row of cost adjoints per lane in LDS: gradient against the FP64
+    oracle; K = 50 > T is one segment of all T iterations."""
+    U, I, m = 2, 1000, 50
+    print(f"case checkpointed lds sweep K={K} form={form}", flush=True)
+    inst = W.small_instance(U, I, m, seed=K + 3, eps=0.05, T=T, kind="lowrank")
+    C = W.random_costs(U, I, m, 0.1, seed=K)
+    ctx = fr.Context(0)
+    ctx.set_form(form)
+    ctx.set_launch(I, m, 512, 2)
+    assert _lds_rows(fr, ctx, U, I, m, K) == 1
+    prob = device_problem(fr, inst.r, inst.e, inst.eps, T)
+    Cd = torch.from_numpy(C).cuda()
+    out = fr.step(ctx, prob, Cd)
+    dC, _ = fr.backward(ctx, prob, Cd, out["imp"], 1.0, want_dr=False, K=K)
+    gC, _ = oracle.grad(inst.r, inst.e, float(inst.eps), T, C)
+    err = float(np.max(np.abs(dC.double().cpu().numpy() - gC)) / np.max(np.abs(gC)))
+    print(f"  dC {err:.3e} of max", flush=True)
+    assert err <= GRAD_REL
