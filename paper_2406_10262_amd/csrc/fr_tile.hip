@@ -81,14 +81,14 @@ __device__ __forceinline__ float quad_max(float v) {
 
 // ---------------------------------------------------------------------------
 // Column reduction of a wave.  p[c] (c < CT) holds the lane's partial sum of
-// column cg CT + c over its rows.  Step A adds the four quads of each 16-lane
-// row (rotations by 4 and 8, which keep the column group); step B adds the
-// four rows with the two row swaps as a reduce-scatter: after it, lane
-// 16 rho + cg + 4 q holds in z[q] the wave's sum of column slot
-// slot(rho, q) of column group cg (valid where slot_ok).  Only the lanes of
-// quad position 0 (q index of the lane, l & 12 == 0) are the wave's writers:
-// the other three lanes of the row hold the same sums in another rounding
-// order.
+// column cg CT + c over its rows.  Step A adds the four 16-lane rows with the
+// two row swaps as a reduce-scatter (CT values to H1, then H2); step B adds
+// the four quads of each 16-lane row (rotations by 4 and 8, which keep the
+// column group) on the H2 values left.  After it, lane 16 rho + cg + 4 q holds
+// in z[q] the wave's sum of column slot slot(rho, q) of column group cg
+// (valid where slot_ok).  Only the lanes of quad position 0 (q index of the
+// lane, l & 12 == 0) are the wave's writers: the other three lanes of the row
+// hold the same sums in another rounding order.
 template <int CT>
 struct Slots {
     static constexpr int H1 = (CT + 1) / 2;
@@ -105,12 +105,6 @@ struct Slots {
 template <int CT>
 __device__ __forceinline__ void wave_colsum(float (&p)[CT], float (&z)[Slots<CT>::H2]) {
     constexpr int H1 = Slots<CT>::H1, H2 = Slots<CT>::H2;
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int c = 0; c < CT; ++c) p[c] += dpp_mov<kRowRor4>(p[c]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int c = 0; c < CT; ++c) p[c] += dpp_mov<kRowRor8>(p[c]);
     __builtin_amdgcn_sched_barrier(0);
     unsigned x[H1], y[H1];
 #pragma unroll
@@ -131,6 +125,12 @@ __device__ __forceinline__ void wave_colsum(float (&p)[CT], float (&z)[Slots<CT>
     swap16_batch<H2>(x2, y2);
 #pragma unroll
     for (int c = 0; c < H2; ++c) z[c] = __builtin_bit_cast(float, x2[c]) + __builtin_bit_cast(float, y2[c]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < H2; ++c) z[c] += dpp_mov<kRowRor4>(z[c]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < H2; ++c) z[c] += dpp_mov<kRowRor8>(z[c]);
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -198,8 +198,12 @@ __device__ __forceinline__ float team_total(const TLane<CT, W>& t, const float* 
 }
 
 // Per-wave broadcast: the reducing lanes write nv values of their column
-// (vb[v][slot]), every lane then reads the values of its CT columns.
-__device__ __forceinline__ void lds_wave_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// (vb[v][slot]), every lane then reads the values of its CT columns.  The LDS
+// performs one wave's operations in the order they are issued, so the reads
+// see the writes issued before them and a later write cannot overtake them;
+// only the compiler has to keep that order (a compiler barrier, no wait: the
+// first values are used while the rest are still arriving).
+__device__ __forceinline__ void lds_wave_order() { asm volatile("" ::: "memory"); }
 
 template <int CT, int NV>
 __device__ __forceinline__ void spread_cols(float* vb, int rslot, bool has, const float (&val)[NV],
@@ -208,7 +212,7 @@ __device__ __forceinline__ void spread_cols(float* vb, int rslot, bool has, cons
 #pragma unroll
         for (int v = 0; v < NV; ++v) vb[v * 64 + rslot] = val[v];
     }
-    lds_wave_fence();
+    lds_wave_order();
     // 16-byte reads of the group's 16 slots (64-byte aligned), CT of them used
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -222,7 +226,7 @@ __device__ __forceinline__ void spread_cols(float* vb, int rslot, bool has, cons
             if (4 * q + 3 < CT) out[v][4 * q + 3] = x.w;
         }
     }
-    lds_wave_fence();
+    lds_wave_order();
 }
 
 // LDS of one block: column partials (2 parities x 64 slots x W), per-wave
@@ -404,8 +408,7 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
         }
         ++nst;
     };
-    static_assert(RT == 8, "two rows per lane of a quad in the row store");
-    const bool cg0 = t.cg == 0, cg1 = t.cg == 1, cg2 = t.cg == 2;
+    static_assert(RT == 8, "a lane's rows are two 16-byte words of the row store");
     if (store) {
         rv = row_view(a.rows, u, a.T, RT * RG);
         put_stretch(1);
@@ -415,6 +418,7 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
         if (t.w == 0 && t.rcol >= 0 && t.rcol < a.hs) dst[t.rcol] = fmaxf(gd + lg2(vd), kNeg);
     };
     if (hist) put_hist(hist);
+    int kleft = a.K, kc = 0;   // iterations to the next checkpoint, checkpoints written
 
     for (int it = 1; it <= a.T; ++it) {
         // row half-step: u_i = 1 / sum_k Kt_ik v_k (the RT sums interleaved)
@@ -435,10 +439,10 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 #pragma unroll
             for (int j = 0; j < RT; ++j) us[j] = rcp(sr[j]);
         }
-        if (store) {   // lane cg of the quad keeps rows 2 cg, 2 cg + 1
-            const float x0 = cg0 ? us[0] : cg1 ? us[2] : cg2 ? us[4] : us[6];
-            const float x1 = cg0 ? us[1] : cg1 ? us[3] : cg2 ? us[5] : us[7];
-            *(float2*)(rv.us + ((size_t)(it - 1) * RG + t.rg) * RT + 2 * t.cg) = make_float2(x0, x1);
+        if (store) {   // the quad's four lanes hold the same eight values: each stores them all
+            float4* dst = (float4*)(rv.us + ((size_t)(it - 1) * RG + t.rg) * RT);
+            dst[0] = make_float4(us[0], us[1], us[2], us[3]);
+            dst[1] = make_float4(us[4], us[5], us[6], us[7]);
         }
         // column half-step: v_k = b_k / sum_i Kt_ik u_i
         float p[CT];
@@ -481,11 +485,14 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 #pragma unroll
             for (int c = 0; c < CT; ++c) v[c] = out[0][c];
         }
-        if (hist) {
-            if (it % a.K == 0)
-                put_hist(hist + (int64_t)(it / a.K) * a.hs);
-            else if (it == a.T)
+        if (hist) {   // checkpoints every K iterations and the last (a countdown, not a division)
+            if (--kleft == 0) {
+                kleft = a.K;
+                ++kc;
+                put_hist(hist + (int64_t)kc * a.hs);
+            } else if (it == a.T) {
                 put_hist(hist + (int64_t)(a.nck - 1) * a.hs);
+            }
         }
     }
 
@@ -822,8 +829,10 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
         __builtin_amdgcn_sched_barrier(0);
         float uj[RT];
         if constexpr (STORED) {
+            // rows beyond I: the forward's u is finite (its row sums start
+            // from kTiny) and their Kt is 0, so every product with it is 0
 #pragma unroll
-            for (int j = 0; j < RT; ++j) uj[j] = (om[j] > 0.f) ? ucur[j] : 0.f;
+            for (int j = 0; j < RT; ++j) uj[j] = ucur[j];
         } else {
             float sr[RT];
 #pragma unroll
@@ -980,7 +989,7 @@ __device__ __forceinline__ Opd load_opd(const float* Ap, const float* Bp, int sl
 // LDS by direct global-to-LDS loads issued at the start, which complete while
 // the MFMAs run and occupy no registers.  The kernel writes dF/dC: into dC
 // when it is asked for, else into the batch's gradient buffer, from which
-// k_tupd applies the update.
+// the last stretch's epilogue applies the update.
 constexpr int kPre = 6;
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
@@ -993,8 +1002,13 @@ constexpr int kXcds = 8;
 typedef float __attribute__((address_space(1))) gfloat;
 typedef float __attribute__((address_space(3))) lfloat;
 
-template <int IP>
-__global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+// MODE 0 writes gF dF/dC (into dC, or into the batch's gradient buffer);
+// MODE 1 applies Adam and MODE 2 plain ascent to C (and Adam's moments) with
+// the finished gradient in the epilogue of the last stretch, reading the
+// costs from the LDS copy and Adam's moments ahead of their use.
+template <int IP, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tgrad(
+    BwdArgs a, TileBuf tb, int64_t u0, int nb) {
     extern __shared__ float smem[];
     if (a.stop && *a.stop) return;   // the outer loop has ended
     constexpr int NRB = (IP + 255) / 256;   // row blocks per consumer (grid: 8 NRB blocks per 8 consumers)
@@ -1079,69 +1093,102 @@ __global__ __launch_bounds__(256) void k_tgrad(BwdArgs a, TileBuf tb, int64_t u0
         rk[0] = c0ok ? rk[0] : kNeg;
         rk[1] = c1ok ? rk[1] : kNeg;
         // dF/dC = sum over stretches of Kt (.) acc: stretches before the last
-        // add into gout, the last writes it
+        // add into gout, the last writes it (or applies the update)
         const bool first = e == 0, last = e + 1 == ne;
+        if (MODE == 0 || !last) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+            for (int r = 0; r < 2; ++r) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                // one row of cells at a time, addresses formed here (opaque
-                // operands keep them from being hoisted and kept live)
-                const int Io = opaque_s(I), mo = opaque_s(m);
-                const int il = r * 32 + mfma_row(v, l);   // row within the wave's 64
-                const int i = rt0 * 32 + il;
-                if (i < Io) {
-                    const float base = bl[il];
-                    float* gp = opaque_p(gout) + (int64_t)i * mo;
+                for (int v = 0; v < 16; ++v) {
+                    // one row of cells at a time, addresses formed here (opaque
+                    // operands keep them from being hoisted and kept live)
+                    const int Io = opaque_s(I), mo = opaque_s(m);
+                    const int il = r * 32 + mfma_row(v, l);   // row within the wave's 64
+                    const int i = rt0 * 32 + il;
+                    if (i < Io) {
+                        const float base = bl[il];
+                        float* gp = opaque_p(gout) + (int64_t)i * mo;
 #pragma unroll
-                    for (int ct = 0; ct < 2; ++ct) {
-                        const int k = ct * 32 + col;
-                        if (k < mo) {
-                            float g = ex2(fmaf(cl[il * mo + k], a.c2, base) + rk[ct]) * acc[r][ct][v];
-                            if (!first) g += gp[k];
-                            gp[k] = g;
+                        for (int ct = 0; ct < 2; ++ct) {
+                            const int k = ct * 32 + col;
+                            if (k < mo) {
+                                float g = ex2(fmaf(cl[il * mo + k], a.c2, base) + rk[ct]) * acc[r][ct][v];
+                                if (!first) g += gp[k];
+                                gp[k] = g;
+                            }
                         }
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            float bc1 = 1.f, bc2 = 1.f;   // Adam's bias corrections (once per wave, uniform)
+            if (MODE == 1) {
+                const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
+                bc1 = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(
+                    int, (float)(1.0 - pow((double)a.b1, (double)st)))));
+                bc2 = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(
+                    int, (float)(1.0 - pow((double)a.b2, (double)st)))));
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+#pragma unroll
+                for (int v0 = 0; v0 < 16; v0 += 4) {
+                    // the moments of 4 rows, loaded from clamped (in-bounds)
+                    // addresses before any of them is used
+                    float mv[4][2], vv[4][2];
+                    if (MODE == 1) {
+                        const int Io = opaque_s(I), mo = opaque_s(m);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int i = min(rt0 * 32 + r * 32 + mfma_row(v0 + q, l), Io - 1);
+                            const int64_t row = (u * Io + i) * (int64_t)mo;
+#pragma unroll
+                            for (int ct = 0; ct < 2; ++ct) {
+                                const int k = min(ct * 32 + col, mo - 1);
+                                mv[q][ct] = opaque_p(a.mom)[row + k];
+                                vv[q][ct] = opaque_p(a.vel)[row + k];
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int Io = opaque_s(I), mo = opaque_s(m);
+                        const int il = r * 32 + mfma_row(v0 + q, l);
+                        const int i = rt0 * 32 + il;
+                        if (i < Io) {
+                            const float base = bl[il];
+                            const float* gp = opaque_p(gout) + (int64_t)i * mo;
+                            const int64_t row = (u * Io + i) * (int64_t)mo;
+#pragma unroll
+                            for (int ct = 0; ct < 2; ++ct) {
+                                const int k = ct * 32 + col;
+                                if (k < mo) {
+                                    const float cold = cl[il * mo + k];
+                                    float g = ex2(fmaf(cold, a.c2, base) + rk[ct]) * acc[r][ct][v0 + q];
+                                    if (!first) g += gp[k];
+                                    float c;
+                                    if (MODE == 1) {
+                                        const float gl = -g;   // Adam minimises -F
+                                        const float mn = a.b1 * mv[q][ct] + (1.f - a.b1) * gl;
+                                        const float vn = a.b2 * vv[q][ct] + (1.f - a.b2) * gl * gl;
+                                        opaque_p(a.mom)[row + k] = mn;
+                                        opaque_p(a.vel)[row + k] = vn;
+                                        c = cold - a.lr * (mn / bc1) / (sqrtf(vn / bc2) + a.aeps);
+                                    } else {
+                                        c = cold + a.lr * g;
+                                    }
+                                    opaque_p(a.Cw)[row + k] = c;
+                                }
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
             }
         }
-        (void)last;
         __builtin_amdgcn_wave_barrier();
-    }
-}
-
-// Update of a batch from its gradient buffer: Adam (MODE 1, bias corrections
-// from the step count) or plain ascent (MODE 2), elementwise over the cells
-// of consumers u0 .. u0 + nb - 1.
-template <int IP, int MODE>
-__global__ __launch_bounds__(256) void k_tupd(BwdArgs a, TileBuf tb, int64_t u0, int nb) {
-    if (a.stop && *a.stop) return;   // the outer loop has ended
-    const int b = blockIdx.y;
-    if (b >= nb) return;
-    const int64_t n = (int64_t)a.I * a.m;
-    const int64_t base = (u0 + b) * n;
-    const float* g = tile_view(tb, b, a.T, IP).cb;   // [I][m]
-    float bc1 = 1.f, bc2 = 1.f;
-    if (MODE == 1) {
-        const int64_t st = a.step_ptr ? *a.step_ptr : a.step_const;
-        bc1 = (float)(1.0 - pow((double)a.b1, (double)st));
-        bc2 = (float)(1.0 - pow((double)a.b2, (double)st));
-    }
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const float gr = g[c];
-        const float craw = a.Cw[base + c];
-        if (MODE == 1) {
-            const float gl = -gr;
-            const float mo = a.b1 * a.mom[base + c] + (1.f - a.b1) * gl;
-            const float ve = a.b2 * a.vel[base + c] + (1.f - a.b2) * gl * gl;
-            a.mom[base + c] = mo;
-            a.vel[base + c] = ve;
-            a.Cw[base + c] = craw - a.lr * (mo / bc1) / (sqrtf(ve / bc2) + a.aeps);
-        } else {
-            a.Cw[base + c] = craw + a.lr * gr;
-        }
     }
 }
 
@@ -1173,17 +1220,15 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
         constexpr int NRB = (IP + 255) / 256;
         const int groups = (nb + kXcds - 1) / kXcds;
         if (!a.dC && !a.Cw) continue;
-        // dF/dC into dC when asked for, else into the gradient buffer and applied
-        hipLaunchKernelGGL((k_tgrad<IP>), dim3(groups * kXcds * NRB), dim3(256),
-                           4 * (64 * a.m + 64) * sizeof(float), s, a, tb, u0, nb);
-        if (!a.dC && a.Cw) {
-            const int64_t cells = (int64_t)a.I * a.m;
-            const dim3 ug((unsigned)std::min<int64_t>((cells + 255) / 256, 64), (unsigned)nb);
-            if (a.rule == 0)
-                hipLaunchKernelGGL((k_tupd<IP, 1>), ug, dim3(256), 0, s, a, tb, u0, nb);
-            else
-                hipLaunchKernelGGL((k_tupd<IP, 2>), ug, dim3(256), 0, s, a, tb, u0, nb);
-        }
+        // dF/dC into dC when asked for, else applied to C (Adam or ascent)
+        const dim3 gg(groups * kXcds * NRB);
+        const size_t lds = 4 * (64 * a.m + 64) * sizeof(float);
+        if (a.dC)
+            hipLaunchKernelGGL((k_tgrad<IP, 0>), gg, dim3(256), lds, s, a, tb, u0, nb);
+        else if (a.rule == 0)
+            hipLaunchKernelGGL((k_tgrad<IP, 1>), gg, dim3(256), lds, s, a, tb, u0, nb);
+        else
+            hipLaunchKernelGGL((k_tgrad<IP, 2>), gg, dim3(256), lds, s, a, tb, u0, nb);
     }
 }
 

@@ -95,6 +95,6 @@ def test_autograd_function(fr, setup):
     (2.5 * F).backward()
     out = fr.step(ctx, prob, points["rand"])
     dC, dr = fr.backward(ctx, prob, points["rand"], out["imp"], 2.5, want_dr=True, K=50)
-    assert abs(float(F) / float(d["rand_F"][0]) - 1) <= F_REL
+    assert abs(float(F.detach()) / float(d["rand_F"][0]) - 1) <= F_REL
     assert torch.allclose(C.grad, dC, rtol=0, atol=1e-6 * float(dC.abs().max()))
     assert torch.allclose(r.grad, dr, rtol=0, atol=1e-6 * float(dr.abs().max()))
