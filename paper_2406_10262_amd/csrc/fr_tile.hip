@@ -251,6 +251,10 @@ __device__ __forceinline__ int opaque_s(int x) {
     asm volatile("" : "+s"(x));
     return x;
 }
+__device__ __forceinline__ int opaque_v(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 // A wave-uniform pointer the optimiser cannot see through: addresses formed
 // from it are computed where they are used instead of being hoisted (and
 // kept live, or spilled) across a loop.
@@ -535,10 +539,57 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Column factors for the contraction's BF16 matrix products.  Each FP32 factor
+// x is split into three BF16 pieces, x = hi + mid + lo to within 2^-24 |x|
+// (each piece is the rounding of what the previous ones leave, and every
+// such remainder is exact in FP32), so that the six products hi hi, hi mid,
+// mid hi, hi lo, mid mid, lo hi carry the FP32 product to about 2^-24.
+// Slots are taken in groups of 8 (slots T + 1 .. 8 G - 1 are zero); the K
+// index of slot 8 g + 4 h + j, factor f, within group g is 8 h + 2 j + f,
+// which is what lane 32 h + c supplies as element 2 j + f of its operand in
+// v_mfma_f32_32x32x16_bf16.  Word bcol_word(g, p, h, c, j) holds piece p of
+// (factor 0, factor 1) of column c, factor 0 in the low half, so a lane
+// reads its whole operand with one 16-byte load.
+__host__ __device__ constexpr int tile_bgroups(int T) { return (T + 8) / 8; }
+__host__ __device__ constexpr size_t tile_bcol_words(int T) {
+    return (size_t)tile_bgroups(T) * 3 * 2 * 64 * 4;
+}
+__device__ __forceinline__ size_t bcol_word(int g, int p, int h, int c, int j) {
+    return ((((size_t)g * 3 + p) * 2 + h) * 64 + c) * 4 + j;
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// (x0, x1) = p[0] + p[1] + p[2], each word a pair of BF16 rounded to nearest
+// (x0 in the low half).
+__device__ __forceinline__ void bf16_split3(float x0, float x1, uint32_t (&p)[3]) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const f32x2 v = {x0, x1};
+        const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+        p[q] = w;
+        x0 -= __builtin_bit_cast(float, w << 16);
+        x1 -= __builtin_bit_cast(float, w & 0xffff0000u);
+    }
+}
+
+// the column factors (w0, w1) of slot s, column c
+__device__ __forceinline__ void put_bcol(uint32_t* Bs, int s, int c, float w0, float w1) {
+    uint32_t p[3];
+    bf16_split3(w0, w1, p);
+    const int g = s >> 3, h = (s >> 2) & 1, j = s & 3;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Bs[bcol_word(g, q, h, c, j)] = p[q];
+}
+
+// ---------------------------------------------------------------------------
 // Per-consumer area of the tile buffer (TileBuf in fr_internal.h).
 struct TileView {
-    float* A;     // [T+1][2][IP]  row factors per iteration (slot T: initial term)
-    float* B;     // [T+1][2][64]  column factors
+    float* A;      // [T+1][2][IP]  row factors per iteration (slot T: initial term)
+    uint32_t* Bs;  // [G][3][2][64][4]  column factors as BF16 pieces (bcol_word)
     float* rho;   // [kTileEpochs][64]  reference column potentials
     float* phi;   // [kTileEpochs][IP]  reference row offsets
     float* off;   // [IP]  row centring offsets of the scaled costs
@@ -552,8 +603,8 @@ __device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int 
     size_t o = 0;
     v.A = (float*)(base + o);
     o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
-    v.B = (float*)(base + o);
-    o += sizeof(float) * (size_t)(T + 1) * 2 * 64;
+    v.Bs = (uint32_t*)(base + o);
+    o += sizeof(uint32_t) * tile_bcol_words(T);
     v.rho = (float*)(base + o);
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     v.phi = (float*)(base + o);
@@ -786,9 +837,9 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
                 if (a.dr && i < I) a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * (xs / a.inv_eps);
             }
         }
-        if (t.w == 0 && t.rcol >= 0) {
-            tv.B[(size_t)(T * 2 + 0) * 64 + t.rcol] = ev;
-            tv.B[(size_t)(T * 2 + 1) * 64 + t.rcol] = 0.f;
+        if (t.w == 0 && t.rcol >= 0) {   // slot T, then the group's unused slots (zero)
+            put_bcol(tv.Bs, T, t.rcol, ev, 0.f);
+            for (int s = T + 1; s < 8 * tile_bgroups(T); ++s) put_bcol(tv.Bs, s, t.rcol, 0.f, 0.f);
         }
         float p[CT];
 #pragma unroll
@@ -908,10 +959,7 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
             A0[4 * RG] = u1;
             A1[4 * RG] = a1;
         }
-        if (t.w == 0 && t.rcol >= 0) {
-            tv.B[(size_t)((tt - 1) * 2 + 0) * 64 + t.rcol] = wg;
-            tv.B[(size_t)((tt - 1) * 2 + 1) * 64 + t.rcol] = wd;
-        }
+        if (t.w == 0 && t.rcol >= 0) put_bcol(tv.Bs, tt - 1, t.rcol, wg, wd);
         if (!more) break;   // gbar after the first iteration is not needed
         float p[CT];
 #pragma unroll
@@ -953,44 +1001,66 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
 
 // ---------------------------------------------------------------------------
 // Contraction of the sweep's factors.  Block (b, rb): 4 waves, wave v takes
-// the 32-row tile rt = 4 rb + v of consumer u0 + b and both 32-column tiles.
-// Result lane layout of v_mfma_f32_32x32x2f32 (checked on the device): lane l
-// holds D[row][l % 32] for row = (v % 4) + 8 (v / 4) + 4 (l / 32), v < 16; it
-// supplies A[l % 32][l / 32] and B[l / 32][l % 32].
+// the row tiles 2 (4 rb + v) and 2 (4 rb + v) + 1 (64 rows) of consumer
+// u0 + b and both 32-column tiles.  Per stretch it sums, over the stretch's
+// slots s and factors f, A[s][f][i] B[s][f][k] with v_mfma_f32_32x32x16_bf16
+// on the three-piece BF16 split of both factors (six products, see
+// bf16_split3): a group of 8 slots is 16 K values, 24 MFMAs per wave.  The
+// row factors are read in FP32 and split here; the column factors come split
+// from the sweep.
+// Result lane layout of the 32x32 MFMAs (checked on the device): lane l
+// holds D[row][l % 32] for row = (v % 4) + 8 (v / 4) + 4 (l / 32), v < 16;
+// in the x16 BF16 form lane l supplies A[l % 32][8 (l / 32) + q] and
+// B[8 (l / 32) + q][l % 32] as its operand elements q < 8.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int mfma_row(int v, int l) { return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5); }
+// the same, formed where it is used (the lane's part opaque, so that the
+// epilogue's 32 row indices are not hoisted and kept live across the MFMA loop)
+__device__ __forceinline__ int mfma_row_here(int v, int l) { return (v & 3) + 8 * (v >> 2) + opaque_v(4 * (l >> 5)); }
 
-// Operands of one slot for the wave's two row tiles (A) and two column tiles
-// (B), loaded raw; the MFMAs that use them mask padded columns to 0 and, for
-// a slot past the end of the stretch, A to 0 (its MFMAs then add exactly 0).
-// Masking at the use keeps the loads in flight until then.
-struct Opd {
-    float a0, a1, b0, b1;
+// Raw buffer resources (stride 0): a load at a byte offset at or past n reads
+// 0 and a store there is dropped (the update epilogue sends the cells outside
+// a consumer's block there).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t buf_rsrc(const void* base, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)n, 0x00020000);
+}
+constexpr int kOffNone = 0x7ffffff0;   // past every range used here
+
+// Operands of one group of 8 slots, loaded raw: the lane's row factors of
+// its 4 slots (both row tiles, both factors) in FP32 and the column factors'
+// BF16 pieces (both column tiles).  The MFMAs mask slots outside the stretch.
+struct GOpd {
+    float a[2][4][2];   // [row tile][slot 4 h + j][factor]
+    u32x4 b[2][3];      // [column tile][piece]
 };
 
+// Ap: A + (row of tile 0); Bp: Bs + bcol_word(0, 0, h, col, 0); slots past T
+// are read at T
 template <int IP>
-__device__ __forceinline__ Opd load_opd(const float* Ap, const float* Bp, int sl) {
-    Opd o;
-    o.a0 = Ap[(size_t)sl * 2 * IP];
-    o.a1 = Ap[(size_t)sl * 2 * IP + 32];
-    o.b0 = Bp[(size_t)sl * 128];
-    o.b1 = Bp[(size_t)sl * 128 + 32];
-    return o;
+__device__ __forceinline__ void load_gopd(GOpd& o, const float* Ap, const uint32_t* Bp, int g, int h, int T) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int sl = min(8 * g + 4 * h + j, T);
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) o.a[r][j][f] = Ap[((size_t)sl * 2 + f) * IP + 32 * r];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int pc = 0; pc < 3; ++pc)
+            o.b[ct][pc] = *(const u32x4*)(Bp + bcol_word(g, pc, 0, 32 * ct, 0));
 }
 
-// Block (b, rb): 4 waves; wave v takes the row tiles 2 (4 rb + v) and
-// 2 (4 rb + v) + 1 (64 rows) of consumer u0 + b and both 32-column tiles, so
-// each slot costs 4 MFMAs for 2 row and 2 column operand loads.  Operands are
-// loaded kPre slots ahead of the MFMAs that use them.
-//
 // The epilogue needs the costs of the wave's 64 rows (the reference kernel
 // Kt = 2^(c c2 - off + rho + phi) is rebuilt from them): they are copied into
 // LDS by direct global-to-LDS loads issued at the start, which complete while
 // the MFMAs run and occupy no registers.  The kernel writes dF/dC: into dC
 // when it is asked for, else into the batch's gradient buffer, from which
 // the last stretch's epilogue applies the update.
-constexpr int kPre = 6;
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // The linear block id is mapped so that the NRB row blocks of one consumer
@@ -1043,8 +1113,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                  0, 0);
         }
     }
-    const float* Ap = tv.A + (size_t)half * IP + rt0 * 32 + col;   // + slot * 2 IP (+ 32)
-    const float* Bp = tv.B + (size_t)half * 64 + col;              // + slot * 128 (+ 32)
+    const float* Ap = tv.A + rt0 * 32 + col;
+    const uint32_t* Bp = tv.Bs + bcol_word(0, 0, half, col, 0);
     const int ne = min(tv.ep[0], kTileEpochs);
     float* gout = a.dC ? a.dC + u * (int64_t)I * m : tv.cb;   // [I][m]
 
@@ -1052,38 +1122,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int hi = tv.ep[1 + e];                    // first (largest) t of the stretch
         const int lo = (e + 1 < ne) ? tv.ep[2 + e] : 0; // first t of the next stretch
         // slots lo .. hi-1 (iterations lo+1 .. hi), then the initial term in stretch 0
-        const int n = hi - lo + (e == 0 ? 1 : 0);
-        auto slot = [&](int q) { return (q >= n || (e == 0 && q == n - 1)) ? T : lo + q; };
+        // groups g0 .. g1-1 hold slots lo .. hi-1; slot T (the initial term,
+        // stretch 0) may sit in a group of its own after them
+        const int g0 = lo >> 3;
+        const int g1 = hi > lo ? ((hi - 1) >> 3) + 1 : g0;
+        const int ng = g1 - g0 + ((e == 0 && (T >> 3) >= g1) ? 1 : 0);
+        auto grp = [&](int q) { return q < g1 - g0 ? g0 + q : (T >> 3); };
         f32x16 acc[2][2] = {};
-        // two operand buffers, alternating: one group's loads are in flight
-        // while the other group's MFMAs run (slots past n have A = 0)
-        Opd p0[kPre], p1[kPre];
-        auto load_group = [&](Opd (&buf)[kPre], int g) {
+        auto mfma_grp = [&](const GOpd& o, int q) __attribute__((always_inline)) {
+            const int g = grp(q);
+            bool ok[4];
 #pragma unroll
-            for (int q = 0; q < kPre; ++q) buf[q] = load_opd<IP>(Ap, Bp, slot(g + q));
-        };
-        auto mfma_group = [&](const Opd (&buf)[kPre], int g) {
+            for (int j = 0; j < 4; ++j) {
+                const int sl = 8 * g + 4 * half + j;
+                ok[j] = (sl >= lo && sl < hi) || (e == 0 && sl == T);
+            }
+            // per row tile: split its factors, then the six products, smallest
+            // first: lo hi, mid mid, hi lo, mid hi, hi mid, hi hi
 #pragma unroll
-            for (int q = 0; q < kPre; ++q) {
-                const bool ok = g + q < n;
-                const float a0 = ok ? buf[q].a0 : 0.f, a1 = ok ? buf[q].a1 : 0.f;
-                const float b0 = c0ok ? buf[q].b0 : 0.f, b1 = c1ok ? buf[q].b1 : 0.f;
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            for (int r = 0; r < 2; ++r) {
+                uint32_t pa[3][4];   // [piece][word j]
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t w[3];
+                    bf16_split3(ok[j] ? o.a[r][j][0] : 0.f, ok[j] ? o.a[r][j][1] : 0.f, w);
+#pragma unroll
+                    for (int pc = 0; pc < 3; ++pc) pa[pc][j] = w[pc];
+                }
+                constexpr int kPa[6] = {2, 1, 0, 1, 0, 0}, kPb[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr) {
+                    const u32x4 av = {pa[kPa[pr]][0], pa[kPa[pr]][1], pa[kPa[pr]][2], pa[kPa[pr]][3]};
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, o.b[ct][kPb[pr]]),
+                            acc[r][ct], 0, 0, 0);
+                }
             }
         };
-        load_group(p0, 0);
-        for (int g = 0; g < n; g += 2 * kPre) {
-            load_group(p1, g + kPre);
-            __builtin_amdgcn_sched_barrier(0);
-            mfma_group(p0, g);
-            __builtin_amdgcn_sched_barrier(0);
-            load_group(p0, g + 2 * kPre);
-            __builtin_amdgcn_sched_barrier(0);
-            mfma_group(p1, g + kPre);
-            __builtin_amdgcn_sched_barrier(0);
+        // two operand buffers, alternating: one group's loads are in flight
+        // while the other group's MFMAs run.  The loop body has no branch (a
+        // load skipped on one path would make the wait before the next MFMAs
+        // count every load in flight); its last load reads a group past the
+        // stretch, which is not used.
+        if (ng > 0) {
+            GOpd p0, p1;
+            load_gopd<IP>(p0, Ap, Bp, grp(0), half, T);
+            int q = 0;
+            for (; q + 1 < ng; q += 2) {
+                load_gopd<IP>(p1, Ap, Bp, grp(q + 1), half, T);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_grp(p0, q);
+                __builtin_amdgcn_sched_barrier(0);
+                load_gopd<IP>(p0, Ap, Bp, grp(q + 2), half, T);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_grp(p1, q + 1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (q < ng) mfma_grp(p0, q);
         }
         // the stretch's row term phi - off of the wave's 64 rows
         bl[l] = tv.phi[e * IP + rt0 * 32 + l] - tv.off[rt0 * 32 + l];
@@ -1103,7 +1200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     // one row of cells at a time, addresses formed here (opaque
                     // operands keep them from being hoisted and kept live)
                     const int Io = opaque_s(I), mo = opaque_s(m);
-                    const int il = r * 32 + mfma_row(v, l);   // row within the wave's 64
+                    const int il = r * 32 + mfma_row_here(v, l);   // row within the wave's 64
                     const int i = rt0 * 32 + il;
                     if (i < Io) {
                         const float base = bl[il];
@@ -1130,63 +1227,78 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 bc2 = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(
                     int, (float)(1.0 - pow((double)a.b2, (double)st)))));
             }
+            // The consumer's [I][m] blocks of C, Adam's moments and the running
+            // adjoint as buffer resources: a cell outside the block (row past
+            // I, padded column) takes an offset past the range, so its loads
+            // read 0 and its stores are dropped, with no branch.  The 64 cells
+            // of a lane go in 8 chunks of 4 rows; each chunk's loads are issued
+            // one chunk ahead of its arithmetic.
+            const uint32_t nb = (uint32_t)(I * m * 4);
+            const int64_t cu = u * (int64_t)I * m;
+            const rsrc_t rC = buf_rsrc(a.Cw + cu, nb);
+            const rsrc_t rM = buf_rsrc(MODE == 1 ? a.mom + cu : a.Cw + cu, nb);
+            const rsrc_t rV = buf_rsrc(MODE == 1 ? a.vel + cu : a.Cw + cu, nb);
+            const rsrc_t rG = buf_rsrc(gout, nb);
+            auto cell_off = [&](int c, int q, int ct) {
+                const int i = rt0 * 32 + (c >> 2) * 32 + mfma_row_here((c & 3) * 4 + q, l);
+                const int k = ct * 32 + col;
+                return (i < I && k < m) ? (i * m + k) * 4 : kOffNone;
+            };
+            auto epi = [&](auto prev) __attribute__((always_inline)) {
+                constexpr bool PREV = decltype(prev)::value;   // add the earlier stretches' adjoint
+                float mv[2][4][2], vv[2][4][2], gq[2][4][2];
+                auto load = [&](int c, int bf) __attribute__((always_inline)) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
+                    for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int v0 = 0; v0 < 16; v0 += 4) {
-                    // the moments of 4 rows, loaded from clamped (in-bounds)
-                    // addresses before any of them is used
-                    float mv[4][2], vv[4][2];
-                    if (MODE == 1) {
-                        const int Io = opaque_s(I), mo = opaque_s(m);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int i = min(rt0 * 32 + r * 32 + mfma_row(v0 + q, l), Io - 1);
-                            const int64_t row = (u * Io + i) * (int64_t)mo;
-#pragma unroll
-                            for (int ct = 0; ct < 2; ++ct) {
-                                const int k = min(ct * 32 + col, mo - 1);
-                                mv[q][ct] = opaque_p(a.mom)[row + k];
-                                vv[q][ct] = opaque_p(a.vel)[row + k];
+                        for (int ct = 0; ct < 2; ++ct) {
+                            const int o = cell_off(c, q, ct);
+                            if (MODE == 1) {
+                                mv[bf][q][ct] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rM, o, 0, 0));
+                                vv[bf][q][ct] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rV, o, 0, 0));
                             }
+                            if (PREV)
+                                gq[bf][q][ct] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rG, o, 0, 0));
+                        }
+                };
+                load(0, 0);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c + 1 < 8) load(c + 1, (c + 1) & 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int bf = c & 1, r = c >> 2;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int il = r * 32 + mfma_row_here((c & 3) * 4 + q, l);   // row within the wave's 64
+                        const float base = bl[il];
+#pragma unroll
+                        for (int ct = 0; ct < 2; ++ct) {
+                            const int o = cell_off(c, q, ct);
+                            // cl[il m + k] stays within the wave's LDS area for k < 64
+                            const float cold = cl[il * m + ct * 32 + col];
+                            float g = ex2(fmaf(cold, a.c2, base) + rk[ct]) * acc[r][ct][(c & 3) * 4 + q];
+                            if (PREV) g += gq[bf][q][ct];
+                            float cn;
+                            if (MODE == 1) {
+                                const float gl = -g;   // Adam minimises -F
+                                const float mn = a.b1 * mv[bf][q][ct] + (1.f - a.b1) * gl;
+                                const float vn = a.b2 * vv[bf][q][ct] + (1.f - a.b2) * gl * gl;
+                                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, mn), rM, o, 0, 0);
+                                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vn), rV, o, 0, 0);
+                                cn = cold - a.lr * (mn / bc1) / (sqrtf(vn / bc2) + a.aeps);
+                            } else {
+                                cn = cold + a.lr * g;
+                            }
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, cn), rC, o, 0, 0);
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int Io = opaque_s(I), mo = opaque_s(m);
-                        const int il = r * 32 + mfma_row(v0 + q, l);
-                        const int i = rt0 * 32 + il;
-                        if (i < Io) {
-                            const float base = bl[il];
-                            const float* gp = opaque_p(gout) + (int64_t)i * mo;
-                            const int64_t row = (u * Io + i) * (int64_t)mo;
-#pragma unroll
-                            for (int ct = 0; ct < 2; ++ct) {
-                                const int k = ct * 32 + col;
-                                if (k < mo) {
-                                    const float cold = cl[il * mo + k];
-                                    float g = ex2(fmaf(cold, a.c2, base) + rk[ct]) * acc[r][ct][v0 + q];
-                                    if (!first) g += gp[k];
-                                    float c;
-                                    if (MODE == 1) {
-                                        const float gl = -g;   // Adam minimises -F
-                                        const float mn = a.b1 * mv[q][ct] + (1.f - a.b1) * gl;
-                                        const float vn = a.b2 * vv[q][ct] + (1.f - a.b2) * gl * gl;
-                                        opaque_p(a.mom)[row + k] = mn;
-                                        opaque_p(a.vel)[row + k] = vn;
-                                        c = cold - a.lr * (mn / bc1) / (sqrtf(vn / bc2) + a.aeps);
-                                    } else {
-                                        c = cold + a.lr * g;
-                                    }
-                                    opaque_p(a.Cw)[row + k] = c;
-                                }
-                            }
-                        }
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
                 }
-            }
+            };
+            if (first)
+                epi(std::false_type{});
+            else
+                epi(std::true_type{});
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1265,7 +1377,7 @@ size_t tile_consumer_bytes(const TileEntry* e, int T) {
     const size_t IP = (size_t)e->imax;
     size_t o = 0;
     o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
-    o += sizeof(float) * (size_t)(T + 1) * 2 * 64;
+    o += sizeof(uint32_t) * tile_bcol_words(T);
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     o += sizeof(float) * (size_t)kTileEpochs * IP;
     o += sizeof(float) * IP;

@@ -82,9 +82,14 @@ def test_tile_backward_scales_with_gF(fr):
     Cd = torch.from_numpy(W.random_costs(U, I, m, 0.05, seed=4)).cuda()
     out = fr.step(ctx, prob, Cd)
     d1, _ = fr.backward(ctx, prob, Cd, out["imp"], 1.0, want_dr=False, K=1)
-    # a power of two scales every product exactly: the results are bitwise -2 d1
-    d2, _ = fr.backward(ctx, prob, Cd, out["imp"], -2.0, want_dr=False, K=1)
-    assert torch.equal(d2, -2.0 * d1)
+    # a positive power of two scales every product and every rounding
+    # exactly: the results are bitwise 2 d1
+    d2, _ = fr.backward(ctx, prob, Cd, out["imp"], 2.0, want_dr=False, K=1)
+    assert torch.equal(d2, 2.0 * d1)
+    # the BF16 matrix products round a sum and its negation differently (by
+    # about an ulp), so gF = -1 gives -d1 to the contraction's rounding
+    d3, _ = fr.backward(ctx, prob, Cd, out["imp"], -1.0, want_dr=False, K=1)
+    assert float((d3 + d1).abs().max()) <= 1e-6 * float(d1.abs().max())
 
 
 @pytest.mark.parametrize("rule", ["gd", "adam"])
