@@ -329,9 +329,12 @@ __device__ __forceinline__ void tile_rebuild(const float* C, int64_t u, int I, i
 
 // Per-consumer area of the row store (RowStore in fr_internal.h), written by
 // the forward for its reverse sweep.  Rows are kept in lane order, row group
-// major ([rg][j], row i = j RG + rg), so that a lane's RT rows are contiguous.
+// major ([rg][j], row i = j RG + rg), so that a lane's RT rows are contiguous;
+// the contraction takes its first row factor from here (slot t - 1 holds u of
+// iteration t, which is that factor; slot T, written by the sweep, the
+// initial term's).
 struct RowView {
-    float* us;    // [T][RG][RT]  row scaling u_i of iteration t = 1..T
+    float* us;    // [T + 1][RG][RT]  row scaling u_i of iteration t = 1..T, then slot T
     float* ph;    // [kTileEpochs][RG][RT]  row offsets of each stretch's kernel
     float* gam;   // [kTileEpochs][64]  column potentials of each stretch's kernel
     int* sep;     // [kTileEpochs + 1]: sep[0] = number of stretches (uncapped),
@@ -343,7 +346,7 @@ __device__ __forceinline__ RowView row_view(const RowStore& rs, int64_t u, int T
     RowView v;
     size_t o = 0;
     v.us = (float*)(base + o);
-    o += sizeof(float) * (size_t)T * IP;
+    o += sizeof(float) * (size_t)(T + 1) * IP;
     v.ph = (float*)(base + o);
     o += sizeof(float) * (size_t)kTileEpochs * IP;
     v.gam = (float*)(base + o);
@@ -588,7 +591,9 @@ __device__ __forceinline__ void put_bcol(uint32_t* Bs, int s, int c, float w0, f
 // ---------------------------------------------------------------------------
 // Per-consumer area of the tile buffer (TileBuf in fr_internal.h).
 struct TileView {
-    float* A;      // [T+1][2][IP]  row factors per iteration (slot T: initial term)
+    float* A1;     // [T+1][IP]  first row factor u per iteration (slot T: initial term), in
+                   // lane order like the row store, which holds it instead when it is kept
+    float* A2;     // [T+1][IP]  second row factor u fbar, in lane order
     uint32_t* Bs;  // [G][3][2][64][4]  column factors as BF16 pieces (bcol_word)
     float* rho;   // [kTileEpochs][64]  reference column potentials
     float* phi;   // [kTileEpochs][IP]  reference row offsets
@@ -601,8 +606,10 @@ __device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int 
     char* base = tb.base + b * tb.stride;
     TileView v;
     size_t o = 0;
-    v.A = (float*)(base + o);
-    o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
+    v.A1 = (float*)(base + o);
+    o += sizeof(float) * (size_t)(T + 1) * IP;
+    v.A2 = (float*)(base + o);
+    o += sizeof(float) * (size_t)(T + 1) * IP;
     v.Bs = (uint32_t*)(base + o);
     o += sizeof(uint32_t) * tile_bcol_words(T);
     v.rho = (float*)(base + o);
@@ -677,7 +684,6 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
     const TileView tv = tile_view(tb, b, T, IP);
     const float* hist = a.hist + u * (int64_t)a.nck * a.hs;
     const int hs = a.hs;
-    const bool cg0 = t.cg == 0, cg1 = t.cg == 1, cg2 = t.cg == 2;
     RowView rv{};
     int f = 0, fstart = 1;   // STORED: the forward's stretch of the current iteration, its first iteration
     float rhod_prev = 0.f;   // STORED: the column potential of stretch f - 1 (reducing lanes)
@@ -831,11 +837,16 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
             fb0[j] = rg[j] * xs;
             qr[j] = rg[j] * qj;
             const int i = j * RG + t.rg;
-            if (t.cg == 0) {
-                tv.A[(size_t)(T * 2 + 0) * IP + i] = -qr[j];
-                tv.A[(size_t)(T * 2 + 1) * IP + i] = 0.f;
-                if (a.dr && i < I) a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * (xs / a.inv_eps);
-            }
+            if (t.cg == 0 && a.dr && i < I) a.dr[u * I + i] = (float)(a.gF / a.imp[i]) * (xs / a.inv_eps);
+        }
+        {   // slot T: the initial term's row factors (-G / (eps s_i), 0), in lane order
+            static_assert(RT == 8, "a lane's rows are two 16-byte words");
+            float* a1 = (STORED ? rv.us : tv.A1) + (size_t)T * IP + t.rg * RT;
+            float* a2 = tv.A2 + (size_t)T * IP + t.rg * RT;
+            *(float4*)a1 = make_float4(-qr[0], -qr[1], -qr[2], -qr[3]);
+            *(float4*)(a1 + 4) = make_float4(-qr[4], -qr[5], -qr[6], -qr[7]);
+            *(float4*)a2 = make_float4(0.f, 0.f, 0.f, 0.f);
+            *(float4*)(a2 + 4) = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (t.w == 0 && t.rcol >= 0) {   // slot T, then the group's unused slots (zero)
             put_bcol(tv.Bs, T, t.rcol, ev, 0.f);
@@ -943,21 +954,20 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
             const float fb = (tt == T ? fb0[j] : 0.f) - uj[j] * d;
             aa[j] = uj[j] * fb;
         }
-        // lane cg of the quad stores rows cg and cg + 4, selected without a
-        // branch: every lane issues the same stores, so that the wait for a
-        // load issued earlier in the pass can count them
+        // the row factors of slot tt - 1 in lane order: u fbar, and u itself
+        // unless the row store holds it.  The quad's four lanes hold the same
+        // eight values and each stores them all (no branch: the wait for a
+        // load issued earlier in the pass can then count these stores).
         {
-            static_assert(RT == 8, "rows cg and cg + 4 of a quad's eight");
-            const float u0 = cg0 ? uj[0] : cg1 ? uj[1] : cg2 ? uj[2] : uj[3];
-            const float u1 = cg0 ? uj[4] : cg1 ? uj[5] : cg2 ? uj[6] : uj[7];
-            const float a0 = cg0 ? aa[0] : cg1 ? aa[1] : cg2 ? aa[2] : aa[3];
-            const float a1 = cg0 ? aa[4] : cg1 ? aa[5] : cg2 ? aa[6] : aa[7];
-            float* A0 = tv.A + (size_t)((tt - 1) * 2 + 0) * IP + t.cg * RG + t.rg;
-            float* A1 = tv.A + (size_t)((tt - 1) * 2 + 1) * IP + t.cg * RG + t.rg;
-            A0[0] = u0;
-            A1[0] = a0;
-            A0[4 * RG] = u1;
-            A1[4 * RG] = a1;
+            static_assert(RT == 8, "a lane's rows are two 16-byte words");
+            float* a2 = tv.A2 + (size_t)(tt - 1) * IP + t.rg * RT;
+            *(float4*)a2 = make_float4(aa[0], aa[1], aa[2], aa[3]);
+            *(float4*)(a2 + 4) = make_float4(aa[4], aa[5], aa[6], aa[7]);
+            if constexpr (!STORED) {
+                float* a1 = tv.A1 + (size_t)(tt - 1) * IP + t.rg * RT;
+                *(float4*)a1 = make_float4(uj[0], uj[1], uj[2], uj[3]);
+                *(float4*)(a1 + 4) = make_float4(uj[4], uj[5], uj[6], uj[7]);
+            }
         }
         if (t.w == 0 && t.rcol >= 0) put_bcol(tv.Bs, tt - 1, t.rcol, wg, wd);
         if (!more) break;   // gbar after the first iteration is not needed
@@ -1002,7 +1012,8 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
 // ---------------------------------------------------------------------------
 // Contraction of the sweep's factors.  Block (b, rb): 4 waves, wave v takes
 // the row tiles 2 (4 rb + v) and 2 (4 rb + v) + 1 (64 rows) of consumer
-// u0 + b and both 32-column tiles.  Per stretch it sums, over the stretch's
+// u0 + b, counted in the row factors' lane order (row S = rg RT + j is plan
+// row j RG + rg), and both 32-column tiles.  Per stretch it sums, over the stretch's
 // slots s and factors f, A[s][f][i] B[s][f][k] with v_mfma_f32_32x32x16_bf16
 // on the three-piece BF16 split of both factors (six products, see
 // bf16_split3): a group of 8 slots is 16 K values, 24 MFMAs per wave.  The
@@ -1036,17 +1047,19 @@ struct GOpd {
     u32x4 b[2][3];      // [column tile][piece]
 };
 
-// Ap: A + (row of tile 0); Bp: Bs + bcol_word(0, 0, h, col, 0); slots past T
-// are read at T
+// A1p, A2p: the two row factors + (row of tile 0); Bp: Bs + bcol_word(0, 0, h,
+// col, 0); slots past T are read at T
 template <int IP>
-__device__ __forceinline__ void load_gopd(GOpd& o, const float* Ap, const uint32_t* Bp, int g, int h, int T) {
+__device__ __forceinline__ void load_gopd(GOpd& o, const float* A1p, const float* A2p, const uint32_t* Bp,
+                                          int g, int h, int T) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int sl = min(8 * g + 4 * h + j, T);
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int r = 0; r < 2; ++r) o.a[r][j][f] = Ap[((size_t)sl * 2 + f) * IP + 32 * r];
+        for (int r = 0; r < 2; ++r) {
+            o.a[r][j][0] = A1p[(size_t)sl * IP + 32 * r];
+            o.a[r][j][1] = A2p[(size_t)sl * IP + 32 * r];
+        }
     }
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
@@ -1078,7 +1091,7 @@ typedef float __attribute__((address_space(3))) lfloat;
 // costs from the LDS copy and Adam's moments ahead of their use.
 template <int IP, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tgrad(
-    BwdArgs a, TileBuf tb, int64_t u0, int nb) {
+    BwdArgs a, TileBuf tb, int64_t u0, int nb, int stored) {
     extern __shared__ float smem[];
     if (a.stop && *a.stop) return;   // the outer loop has ended
     constexpr int NRB = (IP + 255) / 256;   // row blocks per consumer (grid: 8 NRB blocks per 8 consumers)
@@ -1090,10 +1103,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int64_t u = u0 + b;
     const int l = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform in the wave
-    const int rt0 = (rb * 4 + wv) * 2;
+    const int rt0 = (rb * 4 + wv) * 2;   // first row tile, in the row factors' lane order
     const int I = a.I, m = a.m, T = a.T;
-    if (rt0 * 32 >= I) return;
     const TileView tv = tile_view(tb, b, T, IP);
+    // plan row of lane-order row S (S = rg RT + j holds row j RG + rg, RT = 8);
+    // every wave's 64 rows include rows below 4 RG = IP / 2 < I
+    auto prow = [](int S) { return (S & 7) * (IP / 8) + (S >> 3); };
     const int col = l & 31;
     const int half = l >> 5;
     const bool c0ok = col < m, c1ok = 32 + col < m;
@@ -1102,18 +1117,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // row term phi - off of the current stretch
     float* cl = smem + wv * (64 * m + 64);
     float* bl = cl + 64 * m;
-    {
-        const int r0 = rt0 * 32;
-        const int nrow = min(64, I - r0);
-        const int len = nrow * m;   // floats, in [m, 64 m]
-        const float* src = a.C + (u * I + r0) * (int64_t)m;
+    // The wave's 64 rows are 8 runs j = 0..7 of 8 consecutive plan rows
+    // j RG + rg0 .. j RG + rg0 + 7: copied run by run into LDS rows 8 j .. 8 j + 7
+    // (lane-order row S0 + 8 r + j sits in LDS row 8 j + r)
+    for (int j = 0; j < 8; ++j) {
+        const int i0 = j * (IP / 8) + rt0 * 4;
+        const int len = min(8, I - i0) * m;   // floats (none for a run past I)
+        const float* src = a.C + (u * I + i0) * (int64_t)m;
         for (int o = 0; o < len; o += 64) {
             if (o + l < len)
-                __builtin_amdgcn_global_load_lds((const gfloat*)(src + o + l), (lfloat*)(cl + o), 4,
+                __builtin_amdgcn_global_load_lds((const gfloat*)(src + o + l), (lfloat*)(cl + j * 8 * m + o), 4,
                                                  0, 0);
         }
     }
-    const float* Ap = tv.A + rt0 * 32 + col;
+    auto crow = [](int il) { return (il & 7) * 8 + (il >> 3); };   // LDS row of the wave's row il
+    const float* A1p = (stored ? row_view(a.rows, u, T, IP).us : tv.A1) + rt0 * 32 + col;
+    const float* A2p = tv.A2 + rt0 * 32 + col;
     const uint32_t* Bp = tv.Bs + bcol_word(0, 0, half, col, 0);
     const int ne = min(tv.ep[0], kTileEpochs);
     float* gout = a.dC ? a.dC + u * (int64_t)I * m : tv.cb;   // [I][m]
@@ -1168,14 +1187,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // stretch, which is not used.
         if (ng > 0) {
             GOpd p0, p1;
-            load_gopd<IP>(p0, Ap, Bp, grp(0), half, T);
+            load_gopd<IP>(p0, A1p, A2p, Bp, grp(0), half, T);
             int q = 0;
             for (; q + 1 < ng; q += 2) {
-                load_gopd<IP>(p1, Ap, Bp, grp(q + 1), half, T);
+                load_gopd<IP>(p1, A1p, A2p, Bp, grp(q + 1), half, T);
                 __builtin_amdgcn_sched_barrier(0);
                 mfma_grp(p0, q);
                 __builtin_amdgcn_sched_barrier(0);
-                load_gopd<IP>(p0, Ap, Bp, grp(q + 2), half, T);
+                load_gopd<IP>(p0, A1p, A2p, Bp, grp(q + 2), half, T);
                 __builtin_amdgcn_sched_barrier(0);
                 mfma_grp(p1, q + 1);
                 __builtin_amdgcn_sched_barrier(0);
@@ -1183,7 +1202,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             if (q < ng) mfma_grp(p0, q);
         }
         // the stretch's row term phi - off of the wave's 64 rows
-        bl[l] = tv.phi[e * IP + rt0 * 32 + l] - tv.off[rt0 * 32 + l];
+        {
+            const int i = prow(rt0 * 32 + l);
+            bl[l] = tv.phi[e * IP + i] - tv.off[i];
+        }
         __builtin_amdgcn_s_waitcnt(0);   // the cost copy and the row terms are in LDS
         __builtin_amdgcn_wave_barrier();
         float rk[2] = {tv.rho[e * 64 + col], tv.rho[e * 64 + 32 + col]};
@@ -1201,7 +1223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     // operands keep them from being hoisted and kept live)
                     const int Io = opaque_s(I), mo = opaque_s(m);
                     const int il = r * 32 + mfma_row_here(v, l);   // row within the wave's 64
-                    const int i = rt0 * 32 + il;
+                    const int i = prow(rt0 * 32 + il);
                     if (i < Io) {
                         const float base = bl[il];
                         float* gp = opaque_p(gout) + (int64_t)i * mo;
@@ -1209,7 +1231,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                         for (int ct = 0; ct < 2; ++ct) {
                             const int k = ct * 32 + col;
                             if (k < mo) {
-                                float g = ex2(fmaf(cl[il * mo + k], a.c2, base) + rk[ct]) * acc[r][ct][v];
+                                float g = ex2(fmaf(cl[crow(il) * mo + k], a.c2, base) + rk[ct]) * acc[r][ct][v];
                                 if (!first) g += gp[k];
                                 gp[k] = g;
                             }
@@ -1240,7 +1262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const rsrc_t rV = buf_rsrc(MODE == 1 ? a.vel + cu : a.Cw + cu, nb);
             const rsrc_t rG = buf_rsrc(gout, nb);
             auto cell_off = [&](int c, int q, int ct) {
-                const int i = rt0 * 32 + (c >> 2) * 32 + mfma_row_here((c & 3) * 4 + q, l);
+                const int i = prow(rt0 * 32 + (c >> 2) * 32 + mfma_row_here((c & 3) * 4 + q, l));
                 const int k = ct * 32 + col;
                 return (i < I && k < m) ? (i * m + k) * 4 : kOffNone;
             };
@@ -1274,8 +1296,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                         for (int ct = 0; ct < 2; ++ct) {
                             const int o = cell_off(c, q, ct);
-                            // cl[il m + k] stays within the wave's LDS area for k < 64
-                            const float cold = cl[il * m + ct * 32 + col];
+                            // cl[row m + k] stays within the wave's LDS area for k < 64
+                            const float cold = cl[crow(il) * m + ct * 32 + col];
                             float g = ex2(fmaf(cold, a.c2, base) + rk[ct]) * acc[r][ct][(c & 3) * 4 + q];
                             if (PREV) g += gq[bf][q][ct];
                             float cn;
@@ -1323,7 +1345,8 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
     const TileBuf& tb = a.tile;
     for (int64_t u0 = 0; u0 < a.U; u0 += tb.batch) {
         const int nb = (int)((a.U - u0) < tb.batch ? (a.U - u0) : tb.batch);
-        if (a.rows.base && u0 + nb <= a.rows.n)   // the forward kept these consumers' row scalings
+        const int stored = (a.rows.base && u0 + nb <= a.rows.n) ? 1 : 0;
+        if (stored)   // the forward kept these consumers' row scalings
             hipLaunchKernelGGL((k_tbwd<CT, RT, W, true>), dim3(nb), dim3(64 * W),
                                tile_lds_floats<W>(true) * sizeof(float), s, a, tb, u0, nb);
         else
@@ -1336,11 +1359,11 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
         const dim3 gg(groups * kXcds * NRB);
         const size_t lds = 4 * (64 * a.m + 64) * sizeof(float);
         if (a.dC)
-            hipLaunchKernelGGL((k_tgrad<IP, 0>), gg, dim3(256), lds, s, a, tb, u0, nb);
+            hipLaunchKernelGGL((k_tgrad<IP, 0>), gg, dim3(256), lds, s, a, tb, u0, nb, stored);
         else if (a.rule == 0)
-            hipLaunchKernelGGL((k_tgrad<IP, 1>), gg, dim3(256), lds, s, a, tb, u0, nb);
+            hipLaunchKernelGGL((k_tgrad<IP, 1>), gg, dim3(256), lds, s, a, tb, u0, nb, stored);
         else
-            hipLaunchKernelGGL((k_tgrad<IP, 2>), gg, dim3(256), lds, s, a, tb, u0, nb);
+            hipLaunchKernelGGL((k_tgrad<IP, 2>), gg, dim3(256), lds, s, a, tb, u0, nb, stored);
     }
 }
 
@@ -1366,7 +1389,7 @@ const TileEntry* tile_entry(int m, int I) {
 
 size_t tile_row_bytes(const TileEntry* e, int T) {
     const size_t IP = (size_t)e->imax;
-    size_t o = sizeof(float) * (size_t)T * IP;
+    size_t o = sizeof(float) * (size_t)(T + 1) * IP;
     o += sizeof(float) * (size_t)kTileEpochs * IP;
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     o += sizeof(int) * (size_t)(kTileEpochs + 1);
@@ -1376,7 +1399,7 @@ size_t tile_row_bytes(const TileEntry* e, int T) {
 size_t tile_consumer_bytes(const TileEntry* e, int T) {
     const size_t IP = (size_t)e->imax;
     size_t o = 0;
-    o += sizeof(float) * (size_t)(T + 1) * 2 * IP;
+    o += sizeof(float) * (size_t)(T + 1) * 2 * IP;   // A1, A2
     o += sizeof(uint32_t) * tile_bcol_words(T);
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     o += sizeof(float) * (size_t)kTileEpochs * IP;
