@@ -36,11 +36,12 @@
 //   cbar_ik += Kt_ik [u_i (w_k gh_k) + (u_i fbar_i) w_k].
 // The sweep (k_tbwd) therefore never holds cost adjoints: per iteration it
 // forms the row sums sum_k Kt w and sum_k Kt w gh (quad sums), the column sum
-// sum_i Kt (u fbar), and stores the row factors (u, u fbar) and column
-// factors (w gh, w).  k_tgrad then contracts them over the iterations on the
-// matrix cores (FP32 MFMA, 32 x 32 x 2 tiles), multiplies by the reference
-// kernel of each stretch, and applies the update (Adam / ascent) or writes
-// dF/dC.  The initial term -G X / eps at t = T has the same form and is the
+// sum_i Kt (u fbar), and stores the row factor u fbar (u itself is the
+// forward's, kept in the row store) and the column factors (w gh, w).
+// k_tgrad then contracts them over the iterations on the matrix cores (BF16
+// MFMA on three-piece splits of the FP32 factors, 32 x 32 x 16 tiles),
+// multiplies by the reference kernel of each stretch, and applies the update
+// (Adam / ascent) or writes dF/dC.  The initial term -G X / eps at t = T has the same form and is the
 // last slot of the contraction.  A reference is rebased (a new stretch) when
 // a column's w leaves [2^-32, 2^32]; at most kTileEpochs stretches per
 // consumer are stored, beyond which the sweep raises FLAG_EPOCHS.
