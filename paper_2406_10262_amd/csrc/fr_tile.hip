@@ -1040,33 +1040,47 @@ __device__ __forceinline__ rsrc_t buf_rsrc(const void* base, uint32_t n) {
 }
 constexpr int kOffNone = 0x7ffffff0;   // past every range used here
 
-// Operands of one group of 8 slots, loaded raw: the lane's row factors of
-// its 4 slots (both row tiles, both factors) in FP32 and the column factors'
-// BF16 pieces (both column tiles).  The MFMAs mask slots outside the stretch.
+// Row-factor operands of one group of 8 slots, loaded raw: the lane's 4 slots
+// (both row tiles, both factors) in FP32; the MFMAs mask slots outside the
+// stretch.  A1p, A2p: the two row factors + (row of tile 0); slots past T are
+// read at T.  The factors are read once, as a stream (non-temporal: they do
+// not displace the column factors and costs from the caches).
 struct GOpd {
     float a[2][4][2];   // [row tile][slot 4 h + j][factor]
-    u32x4 b[2][3];      // [column tile][piece]
 };
-
-// A1p, A2p: the two row factors + (row of tile 0); Bp: Bs + bcol_word(0, 0, h,
-// col, 0); slots past T are read at T
 template <int IP>
-__device__ __forceinline__ void load_gopd(GOpd& o, const float* A1p, const float* A2p, const uint32_t* Bp,
-                                          int g, int h, int T) {
+__device__ __forceinline__ void load_ga(GOpd& o, const float* A1p, const float* A2p, int g, int h, int T) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int sl = min(8 * g + 4 * h + j, T);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            o.a[r][j][0] = A1p[(size_t)sl * IP + 32 * r];
-            o.a[r][j][1] = A2p[(size_t)sl * IP + 32 * r];
+            o.a[r][j][0] = __builtin_nontemporal_load(A1p + (size_t)sl * IP + 32 * r);
+            o.a[r][j][1] = __builtin_nontemporal_load(A2p + (size_t)sl * IP + 32 * r);
         }
     }
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int pc = 0; pc < 3; ++pc)
-            o.b[ct][pc] = *(const u32x4*)(Bp + bcol_word(g, pc, 0, 32 * ct, 0));
+}
+
+// The column factors of a group are the same for the block's 4 waves: they
+// are staged once per group in LDS, two buffers of 6 chunks (chunk c = 2 p + h,
+// piece p and half h, is 64 columns x 16 bytes at words 256 c of the group),
+// wave v copying chunks v and v + 4 (< 6) through its registers.
+struct GBc {
+    u32x4 c[2];
+};
+__device__ __forceinline__ void load_gbc(GBc& o, const uint32_t* Bs, int g, int wv, int l) {
+    const uint32_t* src = Bs + bcol_word(g, 0, 0, 0, 0) + l * 4;
+    o.c[0] = *(const u32x4*)(src + wv * 256);
+    o.c[1] = *(const u32x4*)(src + min(wv + 4, 5) * 256);
+}
+__device__ __forceinline__ void store_gbc(const GBc& o, uint32_t* dst, int wv, int l) {
+    *(u32x4*)(dst + wv * 256 + l * 4) = o.c[0];
+    if (wv < 2) *(u32x4*)(dst + (wv + 4) * 256 + l * 4) = o.c[1];
+}
+// A block barrier that waits for this wave's LDS operations only, so that
+// its row-factor loads in flight stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // The epilogue needs the costs of the wave's 64 rows (the reference kernel
@@ -1118,6 +1132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // row term phi - off of the current stretch
     float* cl = smem + wv * (64 * m + 64);
     float* bl = cl + 64 * m;
+    uint32_t* bsh = (uint32_t*)(smem + 4 * (64 * m + 64));   // [2][6 chunks][256 words]
     // The wave's 64 rows are 8 runs j = 0..7 of 8 consecutive plan rows
     // j RG + rg0 .. j RG + rg0 + 7: copied run by run into LDS rows 8 j .. 8 j + 7
     // (lane-order row S0 + 8 r + j sits in LDS row 8 j + r)
@@ -1134,7 +1149,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto crow = [](int il) { return (il & 7) * 8 + (il >> 3); };   // LDS row of the wave's row il
     const float* A1p = (stored ? row_view(a.rows, u, T, IP).us : tv.A1) + rt0 * 32 + col;
     const float* A2p = tv.A2 + rt0 * 32 + col;
-    const uint32_t* Bp = tv.Bs + bcol_word(0, 0, half, col, 0);
     const int ne = min(tv.ep[0], kTileEpochs);
     float* gout = a.dC ? a.dC + u * (int64_t)I * m : tv.cb;   // [I][m]
 
@@ -1149,8 +1163,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int ng = g1 - g0 + ((e == 0 && (T >> 3) >= g1) ? 1 : 0);
         auto grp = [&](int q) { return q < g1 - g0 ? g0 + q : (T >> 3); };
         f32x16 acc[2][2] = {};
-        auto mfma_grp = [&](const GOpd& o, int q) __attribute__((always_inline)) {
+        auto mfma_grp = [&](const GOpd& o, const uint32_t* bb, int q) __attribute__((always_inline)) {
             const int g = grp(q);
+            u32x4 bv[2][3];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc)
+                    bv[ct][pc] = *(const u32x4*)(bb + (2 * pc + half) * 256 + (ct * 32 + col) * 4);
             bool ok[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1176,31 +1196,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                     for (int ct = 0; ct < 2; ++ct)
                         acc[r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, o.b[ct][kPb[pr]]),
+                            __builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv[ct][kPb[pr]]),
                             acc[r][ct], 0, 0, 0);
                 }
             }
         };
-        // two operand buffers, alternating: one group's loads are in flight
-        // while the other group's MFMAs run.  The loop body has no branch (a
-        // load skipped on one path would make the wait before the next MFMAs
-        // count every load in flight); its last load reads a group past the
-        // stretch, which is not used.
+        // two operand buffers (registers for the row factors, LDS for the
+        // column factors), alternating: one group's loads are in flight while
+        // the other group's MFMAs run, and its column chunks are written to
+        // the free LDS buffer after them (the barrier that follows also
+        // ensures that every wave is done reading that buffer's previous
+        // group).  The loop body has no branch (a load skipped on one path
+        // would make the wait before the next MFMAs count every load in
+        // flight); its last loads read a group past the stretch, which is not
+        // used.  Every wave of the block runs the same groups.
         if (ng > 0) {
             GOpd p0, p1;
-            load_gopd<IP>(p0, A1p, A2p, Bp, grp(0), half, T);
+            GBc bc;
+            load_gbc(bc, tv.Bs, grp(0), wv, l);
+            load_ga<IP>(p0, A1p, A2p, grp(0), half, T);
+            store_gbc(bc, bsh, wv, l);
+            lds_barrier();
             int q = 0;
             for (; q + 1 < ng; q += 2) {
-                load_gopd<IP>(p1, A1p, A2p, Bp, grp(q + 1), half, T);
+                load_gbc(bc, tv.Bs, grp(q + 1), wv, l);
+                load_ga<IP>(p1, A1p, A2p, grp(q + 1), half, T);
                 __builtin_amdgcn_sched_barrier(0);
-                mfma_grp(p0, q);
+                mfma_grp(p0, bsh, q);
                 __builtin_amdgcn_sched_barrier(0);
-                load_gopd<IP>(p0, A1p, A2p, Bp, grp(q + 2), half, T);
+                store_gbc(bc, bsh + 1536, wv, l);
+                lds_barrier();
+                load_gbc(bc, tv.Bs, grp(q + 2), wv, l);
+                load_ga<IP>(p0, A1p, A2p, grp(q + 2), half, T);
                 __builtin_amdgcn_sched_barrier(0);
-                mfma_grp(p1, q + 1);
+                mfma_grp(p1, bsh + 1536, q + 1);
                 __builtin_amdgcn_sched_barrier(0);
+                store_gbc(bc, bsh, wv, l);
+                lds_barrier();
             }
-            if (q < ng) mfma_grp(p0, q);
+            if (q < ng) mfma_grp(p0, bsh, q);
+            lds_barrier();   // the buffers are free before the next stretch writes them
         }
         // the stretch's row term phi - off of the wave's 64 rows
         {
@@ -1358,7 +1393,7 @@ void launch_tbwd(const BwdArgs& a, int grid, int block, size_t lds, hipStream_t 
         if (!a.dC && !a.Cw) continue;
         // dF/dC into dC when asked for, else applied to C (Adam or ascent)
         const dim3 gg(groups * kXcds * NRB);
-        const size_t lds = 4 * (64 * a.m + 64) * sizeof(float);
+        const size_t lds = (4 * (64 * a.m + 64) + 2 * 1536) * sizeof(float);
         if (a.dC)
             hipLaunchKernelGGL((k_tgrad<IP, 0>), gg, dim3(256), lds, s, a, tb, u0, nb, stored);
         else if (a.rule == 0)
