@@ -447,7 +447,7 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 #pragma unroll
             for (int j = 0; j < RT; ++j) us[j] = rcp(sr[j]);
         }
-        if (store) {   // the quad's four lanes hold the same eight values: each stores them all
+        if (store && t.cg == 0) {   // the quad's four lanes hold the same eight values; one stores them
             float4* dst = (float4*)(rv.us + ((size_t)(it - 1) * RG + t.rg) * RT);
             dst[0] = make_float4(us[0], us[1], us[2], us[3]);
             dst[1] = make_float4(us[4], us[5], us[6], us[7]);
