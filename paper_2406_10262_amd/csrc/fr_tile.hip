@@ -543,29 +543,30 @@ __global__ __launch_bounds__(64 * W) void k_tfwd(FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Column factors for the contraction's BF16 matrix products.  Each FP32 factor
-// x is split into three BF16 pieces, x = hi + mid + lo to within 2^-24 |x|
-// (each piece is the rounding of what the previous ones leave, and every
-// such remainder is exact in FP32), so that the six products hi hi, hi mid,
-// mid hi, hi lo, mid mid, lo hi carry the FP32 product to about 2^-24.
-// Slots are taken in groups of 8 (slots T + 1 .. 8 G - 1 are zero); the K
-// index of slot 8 g + 4 h + j, factor f, within group g is 8 h + 2 j + f,
-// which is what lane 32 h + c supplies as element 2 j + f of its operand in
-// v_mfma_f32_32x32x16_bf16.  Word bcol_word(g, p, h, c, j) holds piece p of
-// (factor 0, factor 1) of column c, factor 0 in the low half, so a lane
-// reads its whole operand with one 16-byte load.
+// Factors for the contraction's BF16 matrix products.  Each FP32 factor x is
+// split into three BF16 pieces, x = hi + mid + lo to within 2^-24 |x| (each
+// piece is the rounding of what the previous ones leave, and every such
+// remainder is exact in FP32), so that the six products hi hi, hi mid, mid hi,
+// hi lo, mid mid, lo hi carry the FP32 product to about 2^-24.  Slots are
+// taken in groups of 8; the K index of slot 8 g + 4 h + j, factor f, within
+// group g is 8 h + 2 j + f, which is what lane 32 h + c supplies as element
+// 2 j + f of its operand in v_mfma_f32_32x32x16_bf16.  The sweep writes the
+// column factors in FP32, [slot][factor][64 columns] (slots T + 1 .. 8 G - 1
+// zero); the contraction splits each group's into LDS, where word
+// bcol_lds(p, h, c, j) holds piece p of (factor 0, factor 1) of slot
+// 8 g + 4 h + j, column c, factor 0 in the low half, so that a lane reads its
+// operand of one piece with one 16-byte load.
 __host__ __device__ constexpr int tile_bgroups(int T) { return (T + 8) / 8; }
-__host__ __device__ constexpr size_t tile_bcol_words(int T) {
-    return (size_t)tile_bgroups(T) * 3 * 2 * 64 * 4;
+__host__ __device__ constexpr size_t tile_bcol_floats(int T) {
+    return (size_t)tile_bgroups(T) * 8 * 2 * 64;
 }
-__device__ __forceinline__ size_t bcol_word(int g, int p, int h, int c, int j) {
-    return ((((size_t)g * 3 + p) * 2 + h) * 64 + c) * 4 + j;
-}
+__device__ __forceinline__ int bcol_lds(int p, int h, int c, int j) { return ((p * 2 + h) * 64 + c) * 4 + j; }
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // (x0, x1) = p[0] + p[1] + p[2], each word a pair of BF16 rounded to nearest
 // (x0 in the low half).
@@ -581,12 +582,9 @@ __device__ __forceinline__ void bf16_split3(float x0, float x1, uint32_t (&p)[3]
 }
 
 // the column factors (w0, w1) of slot s, column c
-__device__ __forceinline__ void put_bcol(uint32_t* Bs, int s, int c, float w0, float w1) {
-    uint32_t p[3];
-    bf16_split3(w0, w1, p);
-    const int g = s >> 3, h = (s >> 2) & 1, j = s & 3;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Bs[bcol_word(g, q, h, c, j)] = p[q];
+__device__ __forceinline__ void put_bcol(float* Bf, int s, int c, float w0, float w1) {
+    Bf[(size_t)(2 * s) * 64 + c] = w0;
+    Bf[(size_t)(2 * s + 1) * 64 + c] = w1;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,7 +593,7 @@ struct TileView {
     float* A1;     // [T+1][IP]  first row factor u per iteration (slot T: initial term), in
                    // lane order like the row store, which holds it instead when it is kept
     float* A2;     // [T+1][IP]  second row factor u fbar, in lane order
-    uint32_t* Bs;  // [G][3][2][64][4]  column factors as BF16 pieces (bcol_word)
+    float* Bf;     // [8 G][2][64]  column factors (w gh, w) per slot; slots past T zero
     float* rho;   // [kTileEpochs][64]  reference column potentials
     float* phi;   // [kTileEpochs][IP]  reference row offsets
     float* off;   // [IP]  row centring offsets of the scaled costs
@@ -611,8 +609,8 @@ __device__ __forceinline__ TileView tile_view(const TileBuf& tb, int64_t b, int 
     o += sizeof(float) * (size_t)(T + 1) * IP;
     v.A2 = (float*)(base + o);
     o += sizeof(float) * (size_t)(T + 1) * IP;
-    v.Bs = (uint32_t*)(base + o);
-    o += sizeof(uint32_t) * tile_bcol_words(T);
+    v.Bf = (float*)(base + o);
+    o += sizeof(float) * tile_bcol_floats(T);
     v.rho = (float*)(base + o);
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     v.phi = (float*)(base + o);
@@ -850,8 +848,8 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
             *(float4*)(a2 + 4) = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (t.w == 0 && t.rcol >= 0) {   // slot T, then the group's unused slots (zero)
-            put_bcol(tv.Bs, T, t.rcol, ev, 0.f);
-            for (int s = T + 1; s < 8 * tile_bgroups(T); ++s) put_bcol(tv.Bs, s, t.rcol, 0.f, 0.f);
+            put_bcol(tv.Bf, T, t.rcol, ev, 0.f);
+            for (int s = T + 1; s < 8 * tile_bgroups(T); ++s) put_bcol(tv.Bf, s, t.rcol, 0.f, 0.f);
         }
         float p[CT];
 #pragma unroll
@@ -970,7 +968,7 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
                 *(float4*)(a1 + 4) = make_float4(uj[4], uj[5], uj[6], uj[7]);
             }
         }
-        if (t.w == 0 && t.rcol >= 0) put_bcol(tv.Bs, tt - 1, t.rcol, wg, wd);
+        if (t.w == 0 && t.rcol >= 0) put_bcol(tv.Bf, tt - 1, t.rcol, wg, wd);
         if (!more) break;   // gbar after the first iteration is not needed
         float p[CT];
 #pragma unroll
@@ -1062,20 +1060,28 @@ __device__ __forceinline__ void load_ga(GOpd& o, const float* A1p, const float* 
 }
 
 // The column factors of a group are the same for the block's 4 waves: they
-// are staged once per group in LDS, two buffers of 6 chunks (chunk c = 2 p + h,
-// piece p and half h, is 64 columns x 16 bytes at words 256 c of the group),
-// wave v copying chunks v and v + 4 (< 6) through its registers.
+// are split once per group into LDS (two buffers of 1536 words, bcol_lds).
+// Wave v takes the two slots 8 g + 4 h + 2 jp + {0, 1} (h = v & 1, jp = v / 2)
+// of column l: four FP32 loads, two splits, three 8-byte LDS writes.
 struct GBc {
-    u32x4 c[2];
+    float v[2][2];   // [slot][factor]
 };
-__device__ __forceinline__ void load_gbc(GBc& o, const uint32_t* Bs, int g, int wv, int l) {
-    const uint32_t* src = Bs + bcol_word(g, 0, 0, 0, 0) + l * 4;
-    o.c[0] = *(const u32x4*)(src + wv * 256);
-    o.c[1] = *(const u32x4*)(src + min(wv + 4, 5) * 256);
+__device__ __forceinline__ void load_gbc(GBc& o, const float* Bf, int g, int wv, int l) {
+    const int s0 = 8 * g + 4 * (wv & 1) + 2 * (wv >> 1);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int f = 0; f < 2; ++f) o.v[jj][f] = Bf[(size_t)(2 * (s0 + jj) + f) * 64 + l];
 }
 __device__ __forceinline__ void store_gbc(const GBc& o, uint32_t* dst, int wv, int l) {
-    *(u32x4*)(dst + wv * 256 + l * 4) = o.c[0];
-    if (wv < 2) *(u32x4*)(dst + (wv + 4) * 256 + l * 4) = o.c[1];
+    uint32_t w[2][3];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) bf16_split3(o.v[jj][0], o.v[jj][1], w[jj]);
+#pragma unroll
+    for (int pc = 0; pc < 3; ++pc) {
+        const u32x2 x = {w[0][pc], w[1][pc]};
+        *(u32x2*)(dst + bcol_lds(pc, wv & 1, l, 2 * (wv >> 1))) = x;
+    }
 }
 // A block barrier that waits for this wave's LDS operations only, so that
 // its row-factor loads in flight stay in flight across it.
@@ -1170,7 +1176,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int pc = 0; pc < 3; ++pc)
-                    bv[ct][pc] = *(const u32x4*)(bb + (2 * pc + half) * 256 + (ct * 32 + col) * 4);
+                    bv[ct][pc] = *(const u32x4*)(bb + bcol_lds(pc, half, ct * 32 + col, 0));
             bool ok[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1213,20 +1219,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         if (ng > 0) {
             GOpd p0, p1;
             GBc bc;
-            load_gbc(bc, tv.Bs, grp(0), wv, l);
+            load_gbc(bc, tv.Bf, grp(0), wv, l);
             load_ga<IP>(p0, A1p, A2p, grp(0), half, T);
             store_gbc(bc, bsh, wv, l);
             lds_barrier();
             int q = 0;
             for (; q + 1 < ng; q += 2) {
-                load_gbc(bc, tv.Bs, grp(q + 1), wv, l);
+                load_gbc(bc, tv.Bf, grp(q + 1), wv, l);
                 load_ga<IP>(p1, A1p, A2p, grp(q + 1), half, T);
                 __builtin_amdgcn_sched_barrier(0);
                 mfma_grp(p0, bsh, q);
                 __builtin_amdgcn_sched_barrier(0);
                 store_gbc(bc, bsh + 1536, wv, l);
                 lds_barrier();
-                load_gbc(bc, tv.Bs, grp(q + 2), wv, l);
+                load_gbc(bc, tv.Bf, grp(q + 2), wv, l);
                 load_ga<IP>(p0, A1p, A2p, grp(q + 2), half, T);
                 __builtin_amdgcn_sched_barrier(0);
                 mfma_grp(p1, bsh + 1536, q + 1);
@@ -1436,7 +1442,7 @@ size_t tile_consumer_bytes(const TileEntry* e, int T) {
     const size_t IP = (size_t)e->imax;
     size_t o = 0;
     o += sizeof(float) * (size_t)(T + 1) * 2 * IP;   // A1, A2
-    o += sizeof(uint32_t) * tile_bcol_words(T);
+    o += sizeof(float) * tile_bcol_floats(T);
     o += sizeof(float) * (size_t)kTileEpochs * 64;
     o += sizeof(float) * (size_t)kTileEpochs * IP;
     o += sizeof(float) * IP;
