@@ -1012,21 +1012,21 @@ __global__ __launch_bounds__(64 * W) void k_tbwd(BwdArgs a, TileBuf tb, int64_t 
 // Contraction of the sweep's factors.  Block (b, rb): 4 waves, wave v takes
 // the row tiles 2 (4 rb + v) and 2 (4 rb + v) + 1 (64 rows) of consumer
 // u0 + b, counted in the row factors' lane order (row S = rg RT + j is plan
-// row j RG + rg), and both 32-column tiles.  Per stretch it sums, over the stretch's
-// slots s and factors f, A[s][f][i] B[s][f][k] with v_mfma_f32_32x32x16_bf16
-// on the three-piece BF16 split of both factors (six products, see
-// bf16_split3): a group of 8 slots is 16 K values, 24 MFMAs per wave.  The
-// row factors are read in FP32 and split here; the column factors come split
-// from the sweep.
+// row j RG + rg), and both 32-column tiles.  Per stretch it sums, over the
+// stretch's slots s and factors f, A[s][f][i] B[s][f][k] with
+// v_mfma_f32_32x32x16_bf16 on the three-piece BF16 split of both factors (six
+// products, see bf16_split3): a group of 8 slots is 16 K values, 24 MFMAs per
+// wave.  Both factors are read in FP32 and split here, the column factors
+// once per block as they are staged in LDS.
 // Result lane layout of the 32x32 MFMAs (checked on the device): lane l
 // holds D[row][l % 32] for row = (v % 4) + 8 (v / 4) + 4 (l / 32), v < 16;
 // in the x16 BF16 form lane l supplies A[l % 32][8 (l / 32) + q] and
 // B[8 (l / 32) + q][l % 32] as its operand elements q < 8.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int mfma_row(int v, int l) { return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5); }
-// the same, formed where it is used (the lane's part opaque, so that the
-// epilogue's 32 row indices are not hoisted and kept live across the MFMA loop)
+// row of result v of lane l, formed where it is used (the lane's part opaque, so
+// that the epilogue's 32 row indices are not hoisted and kept live across the
+// MFMA loop)
 __device__ __forceinline__ int mfma_row_here(int v, int l) { return (v & 3) + 8 * (v >> 2) + opaque_v(4 * (l >> 5)); }
 
 // Raw buffer resources (stride 0): a load at a byte offset at or past n reads
